@@ -1,0 +1,240 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+None of these re-types the oracle's formula: each compares it with a closed
+form, a library routine applied to a special case, an independent brute-force
+double sum over events, or an invariant.  A dropped term, a wrong sign, a wrong
+normalisation or weight, or a wrong index in the oracle fails at least one.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2003_02842_amd import synth
+
+TWO_PI = 2.0 * math.pi
+
+
+# ---------------------------------------------------------------- P1: one jump
+@pytest.mark.parametrize("u", [0.0, 0.25, 0.125, 0.3, 1.0 - 2.0 ** -40, 0.999999])
+def test_single_jump_coefficients(u):
+    """One event (u, delta): c_k = delta * exp(-2 pi i k u) / 2pi for every k
+    (equation F(dp_i)(k), Sec. 2.2)."""
+    delta = 0.37
+    ks = np.array([0, 1, 2, 3, 7, 100, 4999, 5000, 123457])
+    for k in ks:
+        c = oracle.coeffs([u], [delta], 0.0, 1.0, int(k), int(k))[0]
+        # exact-phase reference: reduce k*u in long double-free way via Fraction
+        from fractions import Fraction
+        frac = (Fraction(int(k)) * Fraction(u)) % 1
+        ang = TWO_PI * float(frac)
+        ref = delta * complex(math.cos(ang), -math.sin(ang)) / TWO_PI
+        assert abs(c - ref) <= 1e-15 * abs(delta), (k, c, ref)
+
+
+def test_single_jump_quarter_turn_sign():
+    """u = 1/4: c_1 = -i delta/2pi, c_2 = -delta/2pi, c_3 = +i delta/2pi.
+    Catches a flipped sign of the exponent or a missing 1/2pi."""
+    d = 1.5
+    c = oracle.coeffs([0.25], [d], 0.0, 1.0, 0, 4)
+    expect = np.array([1, -1j, -1, 1j, 1]) * d / TWO_PI
+    np.testing.assert_allclose(c, expect, atol=1e-16)
+
+
+@pytest.mark.parametrize("N", [1, 2, 5, 40, 1000])
+@pytest.mark.parametrize("u", [0.0, 0.4321, 0.999])
+def test_single_jump_estimators(N, u):
+    """Sigma_Dir = delta^2 exactly (Eq. Der:2); Sigma_Fej = delta^2 N/(N+1) with
+    the weights (1-|s|/N)/(N+1) as printed in Eq. Der:3."""
+    d = -0.8
+    coef = oracle.coeffs([u], [d], 0.0, 1.0, 0, N)[None, :]
+    sd, rd = oracle.cov(coef, 1, 1, [N], oracle.DIRICHLET)
+    sf, rf = oracle.cov(coef, 1, 1, [N], oracle.FEJER)
+    assert abs(sd[0, 0, 0, 0] - d * d) <= 1e-14
+    assert abs(sf[0, 0, 0, 0] - d * d * N / (N + 1)) <= 1e-14
+    assert rd[0, 0, 0, 0] == pytest.approx(1.0, abs=1e-15)
+    assert rf[0, 0, 0, 0] == pytest.approx(1.0, abs=1e-15)
+
+
+# ------------------------------------------- P2: brute force over event pairs
+def _brute_sigma(series, N, basis):
+    """Sigma_ij = sum_{h,l} delta^i_h delta^j_l K_N(tilde t^j_l - tilde t^i_h) with the
+    closed-form kernels D_N(x) = sin((N+1/2)x)/sin(x/2) (over 2N+1) and the Fejer
+    sum sum_{|s|<=N} (1-|s|/N) e^{isx} = sin^2(Nx/2)/(N sin^2(x/2)) (over N+1)."""
+    D = len(series)
+    S = np.zeros((D, D))
+    for i in range(D):
+        ui, di = series[i]
+        for j in range(D):
+            uj, dj = series[j]
+            x = TWO_PI * (uj[None, :] - ui[:, None])
+            sx2 = np.sin(x / 2)
+            small = np.abs(sx2) < 1e-12
+            sx2s = np.where(small, 1.0, sx2)
+            if basis == oracle.DIRICHLET:
+                K = np.where(small, 2 * N + 1.0, np.sin((N + 0.5) * x) / sx2s) / (2 * N + 1)
+            else:
+                K = np.where(small, float(N), np.sin(N * x / 2) ** 2 / (N * sx2s ** 2)) / (N + 1)
+            S[i, j] = (di[:, None] * dj[None, :] * K).sum()
+    return S
+
+
+@pytest.mark.parametrize("basis", [oracle.DIRICHLET, oracle.FEJER])
+@pytest.mark.parametrize("N", [1, 3, 17, 64])
+def test_brute_force_double_sum(basis, N):
+    rng = np.random.default_rng(1000 + N)
+    series = []
+    for n in (7, 23, 50, 1):
+        u = np.sort(rng.random(n))
+        series.append((u, rng.normal(size=n) * 0.01))
+    offs = np.cumsum([0] + [len(s[0]) for s in series])
+    t = np.concatenate([s[0] for s in series])
+    dp = np.concatenate([s[1] for s in series])
+    coef = oracle.coeffs_batch(offs, t, dp, 0.0, 1.0, N)
+    S, R = oracle.cov(coef, 1, 4, [N], basis)
+    ref = _brute_sigma(series, N, basis)
+    np.testing.assert_allclose(S[0, 0], ref, rtol=1e-11, atol=1e-15)
+    dref = np.sqrt(np.diag(ref))
+    np.testing.assert_allclose(R[0, 0], ref / np.outer(dref, dref), rtol=1e-10, atol=1e-13)
+
+
+# ------------------------------------------------- P3: equally spaced = DFT
+def test_equally_spaced_is_fft():
+    """u_h = h/n: c_k = FFT(delta)[k mod n]/2pi (synchronous case, Sec. 2.2.3)."""
+    w = synth.bivariate_sync(n=2000, seed=7)
+    n = 2000
+    for s in range(2):
+        _, d = w.series(s)
+        d = d.numpy()
+        F = np.fft.fft(np.concatenate([d, [0.0]]))
+        ks = np.array([0, 1, 2, 999, 1000, 1001, 1999, 2000, 2001, 4321])
+        for k in ks:
+            c = oracle.coeffs(w.t[w.offsets[s]:w.offsets[s + 1]], d, w.t0, w.T, int(k), int(k))[0]
+            assert abs(c - F[k % n] / TWO_PI) <= 1e-13 * np.abs(d).sum()
+
+
+# ---------------------------------------- P4: Hermitian symmetry, real Sigma
+def test_hermitian_symmetry_and_real_sigma():
+    rng = np.random.default_rng(3)
+    N = 40
+    series = [(np.sort(rng.random(n)), rng.normal(size=n)) for n in (30, 45, 12)]
+    offs = np.cumsum([0] + [len(s[0]) for s in series])
+    t = np.concatenate([s[0] for s in series])
+    dp = np.concatenate([s[1] for s in series])
+    full = np.stack([oracle.coeffs(u, d, 0.0, 1.0, -N, N) for u, d in series])
+    # c_{-k} = conj(c_k)
+    np.testing.assert_allclose(full[:, :N][:, ::-1], np.conj(full[:, N + 1:]), rtol=0, atol=1e-15)
+    half = oracle.coeffs_batch(offs, t, dp, 0.0, 1.0, N)
+    np.testing.assert_allclose(full[:, N:], half, rtol=0, atol=1e-15)
+    for basis in (oracle.DIRICHLET, oracle.FEJER):
+        Sc, Rc = oracle.cov_full(full, 1, 3, N, basis)
+        S, R = oracle.cov(half, 1, 3, [N], basis)
+        assert np.abs(Sc.imag).max() <= 1e-15 * np.abs(Sc.real).max()
+        np.testing.assert_allclose(Sc.real[0], S[0, 0], rtol=1e-13, atol=0)
+        np.testing.assert_allclose(S[0, 0], S[0, 0].T, rtol=0, atol=0)
+
+
+# ------------------------------------------------------------------ P5: PSD
+@pytest.mark.parametrize("basis", [oracle.DIRICHLET, oracle.FEJER])
+def test_common_N_estimate_is_psd(basis):
+    """With one N for all assets the weights are >= 0, so Sigma is PSD (Sec. 3.1)."""
+    w = synth.random_events(8, 5, 60, seed=11)
+    N = 25
+    coef = oracle.coeffs_batch(w.offsets, w.t, w.dp, w.t0, w.T, N)
+    S, _ = oracle.cov(coef, 1, 8, [N], basis)
+    ev = np.linalg.eigvalsh(S[0, 0])
+    assert ev.min() >= -1e-12 * ev.max()
+
+
+# ------------------------------------------------------- P6: GBM recovery
+def test_gbm_recovery_within_monte_carlo_error():
+    """Synchronous bivariate GBM with N = n/2: the Dirichlet estimate is the
+    realised covariance, whose mean is the integrated covariance Sigma*T
+    (Sec. 3.2 setting: sigma^2 = (0.1, 0.2), rho = 0.35)."""
+    n, reps = 600, 200
+    ests = []
+    for r in range(reps):
+        w = synth.bivariate_sync(n=n, seed=50_000 + r)
+        _, S, _ = oracle.estimate(w, [n // 2], oracle.DIRICHLET)
+        ests.append(S[0, 0])
+    ests = np.array(ests)
+    mean = ests.mean(0)
+    se = ests.std(0, ddof=1) / math.sqrt(reps)
+    true = w.meta["true_cov"].numpy()
+    assert np.all(np.abs(mean - true) <= 4 * se), (mean, true, se)
+    assert true[0, 1] == pytest.approx(0.35 * math.sqrt(0.1 * 0.2), rel=1e-12)
+
+
+def test_sensitivity_slope_one():
+    """Estimate vs true integrated variance is linear with unit slope (the
+    sensitivity check, Sec. 3.2 footnote)."""
+    n = 800
+    trues, ests = [], []
+    for i, s2 in enumerate(np.linspace(0.1, 0.3, 5)):
+        vals = []
+        for r in range(40):
+            w = synth.bivariate_sync(n=n, seed=70_000 + 100 * i + r, sigma2=(float(s2), 0.2))
+            _, S, _ = oracle.estimate(w, [n // 2], oracle.FEJER)
+            vals.append(S[0, 0, 0, 0])
+        trues.append(s2)
+        ests.append(np.mean(vals))
+    slope = np.polyfit(trues, ests, 1)[0]
+    assert abs(slope - 1.0) < 0.1
+
+
+# ------------------------------------------------------------ P7: invariances
+def test_invariances():
+    rng = np.random.default_rng(5)
+    N = 30
+    series = [(np.sort(rng.random(n)), rng.normal(size=n)) for n in (20, 33, 41)]
+
+    def run(ser, basis=oracle.FEJER):
+        offs = np.cumsum([0] + [len(s[0]) for s in ser])
+        t = np.concatenate([s[0] for s in ser])
+        dp = np.concatenate([s[1] for s in ser])
+        coef = oracle.coeffs_batch(offs, t, dp, 0.0, 1.0, N)
+        S, R = oracle.cov(coef, 1, len(ser), [N], basis)
+        return coef, S[0, 0], R[0, 0]
+
+    c0, S0, R0 = run(series)
+    # circular shift by 1/4 turn: c_k -> c_k e^{-i pi k/2}, Sigma unchanged
+    shifted = [(np.mod(u + 0.25, 1.0), d) for u, d in series]
+    shifted = [(u[np.argsort(u, kind="stable")], d[np.argsort(u, kind="stable")]) for u, d in shifted]
+    c1, S1, _ = run(shifted)
+    k = np.arange(N + 1)
+    np.testing.assert_allclose(c1, c0 * np.exp(-0.5j * np.pi * k)[None, :], atol=1e-13)
+    np.testing.assert_allclose(S1, S0, rtol=1e-12, atol=1e-14)
+    # scaling returns by a scales Sigma by a^2, leaves R
+    a = 3.0
+    _, S2, R2 = run([(u, a * d) for u, d in series])
+    np.testing.assert_allclose(S2, a * a * S0, rtol=1e-13)
+    np.testing.assert_allclose(R2, R0, rtol=1e-12)
+    # permuting assets permutes Sigma
+    perm = [2, 0, 1]
+    _, S3, _ = run([series[p] for p in perm])
+    np.testing.assert_allclose(S3, S0[np.ix_(perm, perm)], rtol=1e-13)
+
+
+def test_zero_series_gives_nan_correlation():
+    offs = np.array([0, 3, 3])
+    t = np.array([0.1, 0.5, 0.9])
+    dp = np.array([0.1, -0.2, 0.3])
+    coef = oracle.coeffs_batch(offs, t, dp, 0.0, 1.0, 5)
+    S, R = oracle.cov(coef, 1, 2, [5], oracle.DIRICHLET)
+    assert S[0, 0, 1, 1] == 0.0 and S[0, 0, 0, 1] == 0.0
+    assert np.isnan(R[0, 0, 0, 1]) and np.isnan(R[0, 0, 1, 1])
+
+
+def test_sweep_matches_individual_cutoffs():
+    """One coefficient set at N_max serves every smaller N: c_k does not depend
+    on N (equation F(dp_i)(k))."""
+    w = synth.random_events(3, 10, 40, seed=9)
+    Ns = [1, 2, 7, 20]
+    coef = oracle.coeffs_batch(w.offsets, w.t, w.dp, w.t0, w.T, 20)
+    S, _ = oracle.cov(coef, 1, 3, Ns, oracle.FEJER)
+    for q, N in enumerate(Ns):
+        cN = oracle.coeffs_batch(w.offsets, w.t, w.dp, w.t0, w.T, N)
+        SN, _ = oracle.cov(cN, 1, 3, [N], oracle.FEJER)
+        np.testing.assert_allclose(S[q], SN[0], rtol=1e-14, atol=1e-18)
