@@ -1,0 +1,157 @@
+/*
+ * mm.h -- C ABI of the MI355X (gfx950) Malliavin-Mancino covariance library.
+ *
+ * The estimator (Chang, Pienaar, Gebbie, "Malliavin-Mancino estimators
+ * implemented with non-uniform fast Fourier transforms") has two stages:
+ *
+ *   1. mm_nufft1: the Fourier coefficients of each series' returns
+ *        c_k = (1/2pi) sum_h delta_h exp(-i k tilde t_h),  k = 0..N
+ *      (Sec. 2.2, the equation defining F(dp_i)(k)), computed by a type-1
+ *      non-uniform FFT (Sec. 2.2.5, Eqs. Der:14-17): spread the events onto an
+ *      oversampled periodic grid with a Gaussian (Eq. Der:5/7, fast Gaussian
+ *      gridding Eq. Der:20), Kaiser-Bessel (Eqs. Der:8-9) or exponential of
+ *      semicircle (Eqs. Der:10-11) kernel, FFT the grid, divide by the kernel's
+ *      Fourier transform.  Negative k follow from c_{-k} = conj(c_k) (real
+ *      returns, Sec. 2.2.2) and are not stored.
+ *
+ *   2. mm_cov: the Dirichlet (Eq. Der:2) or Fejer (Eq. Der:3) estimate
+ *        Sigma_ij = (2pi)^2 sum_{|k|<=N} w_k c_k^(i) conj(c_k^(j))
+ *      with w_k = 1/(2N+1) or (1-|k|/N)/(N+1) (the Fejer weights exactly as
+ *      printed in Eq. Der:3 and step C.2 of the MM algorithm), and the
+ *      correlation R_ij = Sigma_ij / sqrt(Sigma_ii Sigma_jj) (MM algorithm,
+ *      last step).  Several cutoffs N can be evaluated from one coefficient set
+ *      because c_k does not depend on N.
+ *
+ * Conventions for every entry point:
+ *   - Array arguments are DEVICE pointers (gfx950 global memory) owned by the
+ *     caller, except where marked "host".  The library keeps no pointer after
+ *     it returns and never frees caller memory.
+ *   - `stream` is a hipStream_t (NULL: the default stream).  Work is enqueued
+ *     asynchronously on it; results are ready when the stream reaches them.
+ *   - Arguments that the host can check are checked before anything is
+ *     launched; on error nothing is enqueued and the status says why.
+ *   - Nothing throws across this boundary.  Device failures map to MM_ERR_HIP.
+ *   - One process may call from several host threads on different streams;
+ *     calls sharing a workspace buffer must be ordered by the caller.
+ */
+#ifndef MM_H_
+#define MM_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MM_OK = 0,
+    MM_ERR_ARG = 1,          /* a size, pointer or enum argument is invalid */
+    MM_ERR_DATA = 2,         /* validate=1 found unsorted, out-of-window or non-finite events */
+    MM_ERR_TOL = 3,          /* tol outside [1e-14,1e-1] (FP64) or [1e-6,1e-1] (mixed) */
+    MM_ERR_WORKSPACE = 4,    /* ws_bytes below the size the *_workspace_size call reports */
+    MM_ERR_HIP = 5,          /* a HIP runtime call failed */
+    MM_ERR_UNSUPPORTED = 6   /* a valid request this build does not implement */
+} mm_status;
+
+typedef enum { MM_DIRICHLET = 0, MM_FEJER = 1 } mm_basis;            /* Eq. Der:2 / Eq. Der:3 */
+typedef enum { MM_GAUSSIAN = 0, MM_KAISER_BESSEL = 1, MM_ES = 2 } mm_kernel;  /* Eqs. Der:5 / 8-9 / 10-11 */
+typedef enum {
+    MM_PLAIN_FP64 = 0,       /* FP64 everywhere, one launch chain per series, FP64 contraction */
+    MM_MIXED = 1             /* FP64 time reduction and deconvolution factors; FP32 spreading, FFT and
+                                coefficients; contraction on BF16 MFMA with hi/lo split, FP32 accumulate */
+} mm_prec;
+
+/* Optional overrides of the planner (an autotuner's output).  Zero means "let
+ * the planner choose"; pass NULL for all defaults. */
+typedef struct {
+    int32_t width;             /* taps per event (>= 2, <= 40) */
+    double sigma;              /* oversampling factor of the grid, >= 1.25 */
+    int32_t tile;              /* cells per spreading tile (tiled path) */
+    int32_t fused;             /* -1: never use the LDS-resident fused path, 0: auto, 1: prefer it */
+    double es_beta_per_tap;    /* ES shape: beta = es_beta_per_tap * width (paper: 2.3) */
+} mm_tuning;
+
+/* What the planner chose (host only, no device work). */
+typedef struct {
+    int32_t N;                 /* cutoff */
+    int32_t width;             /* taps per event */
+    int32_t msp;               /* spreading half-width M_sp of the paper's rule (Sec. 2.2.5) */
+    int32_t Mr;                /* oversampled grid length (even, 2,3,5-smooth, >= sigma (2N+1)) */
+    int32_t L1, L2;            /* Mr/2 = L1 * L2 (two-pass complex FFT) */
+    int32_t fused;             /* 1: LDS-resident single-workgroup path */
+    int32_t tile;              /* spreading tile of the tiled path */
+    double sigma;              /* oversampling factor used in the kernel shape rules */
+    double beta;               /* ES beta, Gaussian lambda or Kaiser-Bessel b */
+    double tol;
+} mm_plan_info;
+
+/* Plan of a type-1 NUFFT of cutoff N (Sec. 2.2.5): the spreading width follows
+ * the paper's tolerance rules (Sec. 2.2.5, with the ES rule's M_sp + 2), the
+ * grid is Mr = smallest even 2,3,5-smooth length >= max(sigma(2N+1), 2 width, 8)
+ * with sigma = 2 (Sec. 2.2.5), unless `tune` overrides.  Host only. */
+mm_status mm_plan_query(int32_t N, mm_kernel kernel, double tol, mm_prec prec,
+                        const mm_tuning* tune, mm_plan_info* out /* host */);
+
+/* Bytes of device workspace mm_nufft1 needs for S series. */
+mm_status mm_nufft1_workspace_size(int32_t S, int32_t N, mm_kernel kernel, double tol, mm_prec prec,
+                                   const mm_tuning* tune, size_t* bytes /* host */);
+
+/* Type-1 NUFFT of S series (Sec. 2.2.5; coefficients of the equation defining
+ * F(dp_i)(k), Sec. 2.2).
+ *   offsets  int64[S+1], CSR: series s owns events offsets[s] .. offsets[s+1]-1
+ *            (offsets[0] = 0, nondecreasing).  A series may be empty.
+ *   t        float64[E]: event times, nondecreasing within a series, in [t0, T].
+ *            Rescaled as u = (t - t0)/(T - t0) and tilde t = 2 pi u (time-rescaling
+ *            algorithm, appendix); u = 1 is the same point as u = 0.
+ *   dp       float32[E] (dp_is_fp64 = 0) or float64[E] (dp_is_fp64 = 1): the return
+ *            delta_h = p(t_{h+1}) - p(t_h) attached to t_h (left endpoint).
+ *   N        cutoff >= 1; coefficients k = 0..N are produced.
+ *   kernel, tol, prec, tune: see the enums; tol is the target relative l2 error of
+ *            each series' coefficients (Eq. Der:18).
+ *   coef     S x ldc complex, row-major, ldc >= N+1: float2 (MM_MIXED) or double2
+ *            (MM_PLAIN_FP64); column k holds c_k including the 1/2pi factor.
+ *   ws       device workspace of at least mm_nufft1_workspace_size bytes (256-byte aligned).
+ *   validate 1: check the events on the device first (sorted, inside [t0, T], finite),
+ *            which synchronises `stream` and returns MM_ERR_DATA on failure; 0: the
+ *            result for such data is undefined.
+ * Errors: MM_ERR_ARG (S < 0, N < 1, T <= t0, non-finite t0/T, ldc < N+1, NULL
+ * pointers), MM_ERR_TOL, MM_ERR_WORKSPACE, MM_ERR_DATA, MM_ERR_HIP. */
+mm_status mm_nufft1(int32_t S, const int64_t* offsets, const double* t, const void* dp, int32_t dp_is_fp64,
+                    double t0, double T, int32_t N, mm_kernel kernel, double tol, mm_prec prec,
+                    const mm_tuning* tune, void* coef, int64_t ldc, void* ws, size_t ws_bytes,
+                    int32_t validate, void* stream);
+
+/* Bytes of device workspace mm_cov needs (may be 0). */
+mm_status mm_cov_workspace_size(int32_t G, int32_t D, int32_t Nmax, int32_t nN, mm_prec prec,
+                                size_t* bytes /* host */);
+
+/* Dirichlet or Fejer estimates (Eqs. Der:2, Der:3; MM algorithm steps C.1/C.2)
+ * and correlations (MM algorithm, last step) for G groups of D consecutive
+ * series, for each cutoff in Ns.
+ *   coef     (G*D) x ldc complex as written by mm_nufft1 (float2 for MM_MIXED,
+ *            double2 for MM_PLAIN_FP64), columns k = 0..max(Ns).
+ *   Ns       host int32[nN], each in 1..ldc-1, 1 <= nN <= 128.
+ *   cov      nN x G x D x D, row-major: float (MM_MIXED) or double (MM_PLAIN_FP64).
+ *   corr     same shape and type, or NULL.  R_ij is NaN where Sigma_ii <= 0 or
+ *            Sigma_jj <= 0 (an empty series).
+ * Errors: MM_ERR_ARG, MM_ERR_WORKSPACE, MM_ERR_UNSUPPORTED, MM_ERR_HIP. */
+mm_status mm_cov(int32_t G, int32_t D, const void* coef, int64_t ldc, const int32_t* Ns, int32_t nN,
+                 mm_basis basis, mm_prec prec, void* cov, void* corr, void* ws, size_t ws_bytes,
+                 void* stream);
+
+/* Human-readable text of a status (static storage). */
+const char* mm_status_string(mm_status s);
+
+/* Per-kernel timing: when enabled, every kernel the library launches is
+ * bracketed by HIP events on its stream; mm_profile_read synchronises those
+ * events and returns the summed duration and launch count of the kernels whose
+ * name equals `kernel_name` (host string), NULL meaning all. */
+mm_status mm_profile_enable(int32_t on);
+mm_status mm_profile_read(const char* kernel_name, double* total_ms /* host */, int64_t* launches /* host */);
+mm_status mm_profile_reset(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MM_H_ */

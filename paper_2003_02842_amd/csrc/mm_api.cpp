@@ -1,0 +1,258 @@
+// C ABI entry points (include/mm.h): argument checks on the host, plan and
+// workspace carving, then asynchronous launches on the caller's stream.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "mm_internal.h"
+
+namespace mm {
+
+// ------------------------------------------------------------------------- profiling
+namespace {
+struct ProfRec {
+    std::string name;
+    hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof_pending;
+std::vector<hipEvent_t> g_prof_free;
+std::map<std::string, std::pair<double, int64_t>> g_prof_total;
+std::map<std::string, hipEvent_t> g_prof_open;
+
+hipEvent_t take_event()
+{
+    if (!g_prof_free.empty()) {
+        hipEvent_t e = g_prof_free.back();
+        g_prof_free.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+}  // namespace
+
+void prof_begin(const char* name, hipStream_t st)
+{
+    if (!g_prof_on) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    hipEvent_t e = take_event();
+    if (!e) return;
+    hipEventRecord(e, st);
+    g_prof_open[name] = e;
+}
+
+void prof_end(const char* name, hipStream_t st)
+{
+    if (!g_prof_on) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    auto it = g_prof_open.find(name);
+    if (it == g_prof_open.end()) return;
+    hipEvent_t e = take_event();
+    if (!e) return;
+    hipEventRecord(e, st);
+    g_prof_pending.push_back({name, it->second, e});
+    g_prof_open.erase(it);
+}
+
+static void prof_drain()
+{
+    for (auto& r : g_prof_pending) {
+        float ms = 0.f;
+        hipEventSynchronize(r.b);
+        hipEventElapsedTime(&ms, r.a, r.b);
+        auto& tot = g_prof_total[r.name];
+        tot.first += ms;
+        tot.second += 1;
+        g_prof_free.push_back(r.a);
+        g_prof_free.push_back(r.b);
+    }
+    g_prof_pending.clear();
+}
+
+}  // namespace mm
+
+using namespace mm;
+
+static mm_status hip_status(hipError_t e) { return e == hipSuccess ? MM_OK : MM_ERR_HIP; }
+
+extern "C" {
+
+const char* mm_status_string(mm_status s)
+{
+    switch (s) {
+        case MM_OK: return "ok";
+        case MM_ERR_ARG: return "invalid argument";
+        case MM_ERR_DATA: return "invalid event data (unsorted, outside [t0,T] or non-finite)";
+        case MM_ERR_TOL: return "tolerance outside the supported range for this precision";
+        case MM_ERR_WORKSPACE: return "workspace too small";
+        case MM_ERR_HIP: return "HIP runtime error";
+        case MM_ERR_UNSUPPORTED: return "unsupported request";
+    }
+    return "unknown status";
+}
+
+mm_status mm_plan_query(int32_t N, mm_kernel kernel, double tol, mm_prec prec, const mm_tuning* tune,
+                        mm_plan_info* out)
+{
+    if (!out) return MM_ERR_ARG;
+    Plan p;
+    mm_status s = make_plan(N, kernel, tol, prec, tune, &p);
+    if (s != MM_OK) return s;
+    out->N = p.N;
+    out->width = p.kp.w;
+    out->msp = p.msp;
+    out->Mr = p.Mr;
+    out->L1 = p.L1;
+    out->L2 = p.L2;
+    out->fused = p.fused;
+    out->tile = p.tile;
+    out->sigma = p.sigma;
+    out->beta = kernel == MM_ES ? p.kp.es_beta : (kernel == MM_GAUSSIAN ? p.kp.g_lambda : p.kp.kb_b);
+    out->tol = p.tol;
+    return MM_OK;
+}
+
+mm_status mm_nufft1_workspace_size(int32_t S, int32_t N, mm_kernel kernel, double tol, mm_prec prec,
+                                   const mm_tuning* tune, size_t* bytes)
+{
+    if (!bytes || S < 0) return MM_ERR_ARG;
+    Plan p;
+    mm_status s = make_plan(N, kernel, tol, prec, tune, &p);
+    if (s != MM_OK) return s;
+    *bytes = nufft_workspace(p, S).total;
+    return MM_OK;
+}
+
+mm_status mm_nufft1(int32_t S, const int64_t* offsets, const double* t, const void* dp, int32_t dp_is_fp64,
+                    double t0, double T, int32_t N, mm_kernel kernel, double tol, mm_prec prec,
+                    const mm_tuning* tune, void* coef, int64_t ldc, void* ws, size_t ws_bytes, int32_t validate,
+                    void* stream)
+{
+    if (S < 0 || (dp_is_fp64 != 0 && dp_is_fp64 != 1) || (validate != 0 && validate != 1)) return MM_ERR_ARG;
+    if (!isfinite(t0) || !isfinite(T) || !(T > t0)) return MM_ERR_ARG;
+    if (N < 1 || ldc < (int64_t)N + 1) return MM_ERR_ARG;
+    if (S > 0 && (!offsets || !t || !dp || !coef)) return MM_ERR_ARG;
+    if (S > 65535) return MM_ERR_UNSUPPORTED;
+    Plan p;
+    mm_status s = make_plan(N, kernel, tol, prec, tune, &p);
+    if (s != MM_OK) return s;
+    NufftWs w = nufft_workspace(p, S);
+    if (S == 0) return MM_OK;
+    if (!ws || ws_bytes < w.total) return MM_ERR_WORKSPACE;
+    if (((uintptr_t)ws & 255) != 0) return MM_ERR_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    char* wsb = (char*)ws;
+    hipError_t e = launch_prep(p, w, wsb, st);
+    if (e != hipSuccess) return MM_ERR_HIP;
+    if (validate) {
+        int* flag = (int*)(wsb + w.flag);
+        if (hipMemsetAsync(flag, 0, sizeof(int), st) != hipSuccess) return MM_ERR_HIP;
+        e = launch_validate(S, offsets, t, dp, dp_is_fp64, t0, T, flag, st);
+        if (e != hipSuccess) return MM_ERR_HIP;
+        int host_flag = 0;
+        if (hipMemcpyAsync(&host_flag, flag, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess) return MM_ERR_HIP;
+        if (hipStreamSynchronize(st) != hipSuccess) return MM_ERR_HIP;
+        if (host_flag) return MM_ERR_DATA;
+    }
+    if (prec == MM_MIXED) {
+        if (p.fused)
+            e = launch_nufft_fused(p, w, wsb, S, offsets, t, dp, dp_is_fp64, t0, T, coef, ldc, st);
+        else
+            e = launch_nufft_tiled(p, w, wsb, 0, S, offsets, t, dp, dp_is_fp64, t0, T, coef, ldc, st);
+    } else {
+        // plain form: one launch chain per series, grid buffer reused in stream order
+        for (int32_t sidx = 0; sidx < S && e == hipSuccess; ++sidx)
+            e = launch_nufft_tiled(p, w, wsb, sidx, 1, offsets, t, dp, dp_is_fp64, t0, T, coef, ldc, st);
+    }
+    return hip_status(e);
+}
+
+static int small_d_limit(int32_t D) { return D * (D + 1) / 2 <= 1024; }
+
+mm_status mm_cov_workspace_size(int32_t G, int32_t D, int32_t Nmax, int32_t nN, mm_prec prec, size_t* bytes)
+{
+    if (!bytes || G < 1 || D < 1 || Nmax < 1 || nN < 1 || nN > kMaxCutoffs) return MM_ERR_ARG;
+    if (prec != MM_PLAIN_FP64 && prec != MM_MIXED) return MM_ERR_ARG;
+    *bytes = (small_d_limit(D) || prec == MM_PLAIN_FP64) ? 0 : cov_mfma_workspace(G, D, Nmax);
+    return MM_OK;
+}
+
+mm_status mm_cov(int32_t G, int32_t D, const void* coef, int64_t ldc, const int32_t* Ns, int32_t nN, mm_basis basis,
+                 mm_prec prec, void* cov, void* corr, void* ws, size_t ws_bytes, void* stream)
+{
+    if (G < 1 || D < 1 || !coef || !cov || !Ns || nN < 1 || nN > kMaxCutoffs) return MM_ERR_ARG;
+    if (basis != MM_DIRICHLET && basis != MM_FEJER) return MM_ERR_ARG;
+    if (prec != MM_PLAIN_FP64 && prec != MM_MIXED) return MM_ERR_ARG;
+    if ((int64_t)G * D > 65535ll * 65535ll) return MM_ERR_UNSUPPORTED;
+    Cutoffs cut;
+    cut.n = nN;
+    int32_t Nmax = 0;
+    for (int q = 0; q < nN; ++q) {
+        if (Ns[q] < 1 || (int64_t)Ns[q] > ldc - 1) return MM_ERR_ARG;
+        cut.N[q] = Ns[q];
+        Nmax = std::max(Nmax, Ns[q]);
+    }
+    size_t need = 0;
+    mm_cov_workspace_size(G, D, Nmax, nN, prec, &need);
+    if (need > 0 && (!ws || ws_bytes < need)) return MM_ERR_WORKSPACE;
+    if (need > 0 && ((uintptr_t)ws & 255) != 0) return MM_ERR_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    const size_t es = prec == MM_MIXED ? 4 : 8;
+    if (small_d_limit(D)) {
+        if (G > 65535) return MM_ERR_UNSUPPORTED;
+        e = launch_cov_small(prec, G, D, coef, ldc, Nmax, cut, basis, cov, st);
+    } else {
+        for (int q = 0; q < nN && e == hipSuccess; ++q) {
+            char* cq = (char*)cov + (size_t)q * G * D * D * es;
+            if (prec == MM_MIXED)
+                e = launch_cov_mfma(G, D, coef, ldc, Ns[q], basis, cq, (char*)ws, st);
+            else
+                e = launch_cov_fp64(G, D, coef, ldc, Ns[q], basis, cq, st);
+        }
+    }
+    if (e == hipSuccess && corr) e = launch_corr(prec, (int64_t)nN * G, D, cov, corr, st);
+    return hip_status(e);
+}
+
+mm_status mm_profile_enable(int32_t on)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_on = on != 0;
+    return MM_OK;
+}
+
+mm_status mm_profile_read(const char* name, double* total_ms, int64_t* launches)
+{
+    if (!total_ms || !launches) return MM_ERR_ARG;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    prof_drain();
+    double ms = 0;
+    int64_t n = 0;
+    for (auto& kv : g_prof_total)
+        if (!name || kv.first == name) {
+            ms += kv.second.first;
+            n += kv.second.second;
+        }
+    *total_ms = ms;
+    *launches = n;
+    return MM_OK;
+}
+
+mm_status mm_profile_reset(void)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    prof_drain();
+    g_prof_total.clear();
+    return MM_OK;
+}
+
+}  // extern "C"

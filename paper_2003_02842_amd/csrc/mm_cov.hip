@@ -1,0 +1,409 @@
+// gfx950 kernels of the Dirichlet / Fejer contraction (Eqs. Der:2, Der:3; steps
+// C.1/C.2 of the MM algorithm) and the correlation step.
+//
+// With real returns c_{-k} = conj(c_k) (Sec. 2.2.2), so
+//   Sigma_ij = (2pi)^2 sum_{k=0..N} m_k w_k Re(c_k^i conj c_k^j),  m_0 = 1, m_k = 2,
+// a real symmetric product of the D x 2(N+1) matrix X_i,2k+e = s_k (Re,Im)_e c_k^i,
+// s_k = 2pi sqrt(m_k w_k), with itself.
+//
+//   k_cov_small     small D, any number of cutoffs: one workgroup per group of
+//                   series, one thread per (i, j) pair, running FP64 prefix sums
+//                   S0(N) = sum m_k P_k and S1(N) = sum m_k k P_k over k, read off
+//                   at every cutoff (Dirichlet S0/(2N+1), Fejer (S0 - S1/N)/(N+1))
+//   k_split_bf16    X in BF16 hi/lo parts: hi = rne(x), lo = rne(x - hi)
+//   k_syrk_mfma     lower-triangle 128x128 tiles of X X^T on v_mfma_f32_32x32x16_bf16,
+//                   hi*hi + hi*lo + lo*hi with FP32 accumulation, split over k
+//   k_syrk_reduce   sum of the k-splits, mirrored to the full matrix
+//   k_cov_fp64      FP64 tiled product for the plain form
+//   k_corr          R_ij = Sigma_ij / sqrt(Sigma_ii Sigma_jj), NaN if a variance <= 0
+#include <hip/hip_runtime.h>
+
+#include "mm_internal.h"
+
+namespace mm {
+
+static const double kTwoPi = 6.283185307179586476925286766559;
+
+__device__ __forceinline__ double2 to_d2(float2 a) { return make_double2(a.x, a.y); }
+__device__ __forceinline__ double2 to_d2(double2 a) { return a; }
+
+struct SortedCutoffs {
+    int n;
+    int N[kMaxCutoffs];      // ascending
+    int slot[kMaxCutoffs];   // output slot of each
+};
+
+template <typename CT, typename OT>
+__global__ void k_cov_small(int D, const CT* __restrict__ coef, int64_t ldc, int Nmax, SortedCutoffs cut, int basis,
+                            int G, OT* __restrict__ cov)
+{
+    constexpr int KC = 64;
+    extern __shared__ __align__(16) char smem_raw[];
+    double2* sh = reinterpret_cast<double2*>(smem_raw);   // D x KC
+    const int g = blockIdx.x;
+    const int npairs = D * (D + 1) / 2;
+    int pi = -1, pj = -1;
+    if ((int)threadIdx.x < npairs) {
+        int t = threadIdx.x;
+        int i = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+        while (i * (i + 1) / 2 > t) --i;
+        while ((i + 1) * (i + 2) / 2 <= t) ++i;
+        pi = i;
+        pj = t - i * (i + 1) / 2;
+    }
+    double S0 = 0.0, S1 = 0.0;
+    int q = 0;
+    const double fourpi2 = kTwoPi * kTwoPi;
+    for (int k0 = 0; k0 <= Nmax; k0 += KC) {
+        const int kc = min(KC, Nmax + 1 - k0);
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < D * KC; idx += blockDim.x) {
+            int d = idx / KC, kk = idx - d * KC;
+            sh[idx] = (kk < kc) ? to_d2(coef[(int64_t)(g * D + d) * ldc + k0 + kk]) : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+        for (int kk = 0; kk < kc; ++kk) {
+            const int k = k0 + kk;
+            if (pi >= 0) {
+                double2 a = sh[pi * KC + kk], b = sh[pj * KC + kk];
+                double P = a.x * b.x + a.y * b.y;
+                double m = k ? 2.0 : 1.0;
+                S0 += m * P;
+                S1 += m * (double)k * P;
+            }
+            while (q < cut.n && cut.N[q] == k) {
+                if (pi >= 0) {
+                    const double Nd = (double)k;
+                    double v = (basis == MM_DIRICHLET) ? S0 / (2.0 * Nd + 1.0) : (S0 - S1 / Nd) / (Nd + 1.0);
+                    v *= fourpi2;
+                    OT* C = cov + ((int64_t)cut.slot[q] * G + g) * D * D;
+                    C[pi * D + pj] = (OT)v;
+                    C[pj * D + pi] = (OT)v;
+                }
+                ++q;
+            }
+        }
+    }
+}
+
+template <typename OT>
+__global__ void k_corr(int64_t total, int D, const OT* __restrict__ cov, OT* __restrict__ corr)
+{
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    int64_t DD = (int64_t)D * D;
+    int64_t m = idx / DD;
+    int r = (int)(idx - m * DD);
+    int i = r / D, j = r - i * D;
+    const OT* C = cov + m * DD;
+    OT a = C[i * D + i], b = C[j * D + j];
+    corr[idx] = (a > (OT)0 && b > (OT)0) ? C[r] / (sqrt(a) * sqrt(b)) : (OT)NAN;
+}
+
+// ----------------------------------------------------------------------------------- FP64 plain
+constexpr int F64T = 64;   // tile edge
+constexpr int F64K = 16;   // k per stage
+
+__global__ __launch_bounds__(256) void k_cov_fp64(int D, const double2* __restrict__ coef, int64_t ldc, int N,
+                                                  int basis, double* __restrict__ cov)
+{
+    __shared__ double2 sA[F64K][F64T + 1];
+    __shared__ double2 sB[F64K][F64T + 1];
+    // lower-triangle tile enumeration t = bi(bi+1)/2 + bj
+    const int t = blockIdx.x;
+    int bi = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while (bi * (bi + 1) / 2 > t) --bi;
+    while ((bi + 1) * (bi + 2) / 2 <= t) ++bi;
+    const int bj = t - bi * (bi + 1) / 2;
+    const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+    double acc[4][4];
+    for (int u = 0; u < 4; ++u)
+        for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+    const double fourpi2 = kTwoPi * kTwoPi;
+    for (int k0 = 0; k0 <= N; k0 += F64K) {
+        for (int idx = threadIdx.x; idx < F64T * F64K; idx += 256) {
+            int r = idx >> 4, kk = idx & 15;
+            int k = k0 + kk;
+            double wk = 0.0;
+            if (k <= N) {
+                double w = (basis == MM_DIRICHLET) ? 1.0 / (2.0 * N + 1.0)
+                                                   : (1.0 - (double)k / (double)N) / ((double)N + 1.0);
+                wk = (k ? 2.0 : 1.0) * w * fourpi2;
+            }
+            int ia = bi * F64T + r, ib = bj * F64T + r;
+            double2 a = (k <= N && ia < D) ? coef[(int64_t)ia * ldc + k] : make_double2(0.0, 0.0);
+            double2 b = (k <= N && ib < D) ? coef[(int64_t)ib * ldc + k] : make_double2(0.0, 0.0);
+            sA[kk][r] = make_double2(a.x * wk, a.y * wk);
+            sB[kk][r] = b;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int kk = 0; kk < F64K; ++kk) {
+            double2 a[4], b[4];
+            for (int u = 0; u < 4; ++u) a[u] = sA[kk][ty * 4 + u];
+            for (int v = 0; v < 4; ++v) b[v] = sB[kk][tx * 4 + v];
+            for (int u = 0; u < 4; ++u)
+                for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u].x, b[v].x, fma(a[u].y, b[v].y, acc[u][v]));
+        }
+        __syncthreads();
+    }
+    for (int u = 0; u < 4; ++u)
+        for (int v = 0; v < 4; ++v) {
+            int i = bi * F64T + ty * 4 + u, j = bj * F64T + tx * 4 + v;
+            if (i < D && j < D) {
+                cov[(int64_t)i * D + j] = acc[u][v];
+                cov[(int64_t)j * D + i] = acc[u][v];
+            }
+        }
+}
+
+// ------------------------------------------------------------------------------ split-BF16 MFMA
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int ST = 128;         // output tile edge
+constexpr int SK = 32;          // k (real columns) per LDS stage
+constexpr int SLD = SK + 8;     // padded LDS row, bf16 elements
+
+__device__ __forceinline__ uint16_t bf16_rne(float x)
+{
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf16_to_f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// X (Dp x Kp, zero padded) from float2 coefficients: column 2k+e = s_k (Re, Im)_e c_k.
+__global__ void k_split_bf16(int D, int Dp, const float2* __restrict__ coef, int64_t ldc, int N, int basis,
+                             int64_t Kp, uint16_t* __restrict__ hi, uint16_t* __restrict__ lo)
+{
+    const int64_t row = blockIdx.y;
+    const double Nd = (double)N;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < Kp / 2; c += (int64_t)gridDim.x * blockDim.x) {
+        float2 v = make_float2(0.f, 0.f);
+        int k = (int)c;
+        if (row < D && k <= N) {
+            double w = (basis == MM_DIRICHLET) ? 1.0 / (2.0 * Nd + 1.0) : (1.0 - (double)k / Nd) / (Nd + 1.0);
+            float s = (float)(kTwoPi * sqrt((k ? 2.0 : 1.0) * w));
+            float2 cc = coef[row * ldc + k];
+            v = make_float2(cc.x * s, cc.y * s);
+        }
+        uint16_t h0 = bf16_rne(v.x), h1 = bf16_rne(v.y);
+        uint16_t l0 = bf16_rne(v.x - bf16_to_f(h0)), l1 = bf16_rne(v.y - bf16_to_f(h1));
+        *(uint32_t*)&hi[row * Kp + 2 * c] = (uint32_t)h0 | ((uint32_t)h1 << 16);
+        *(uint32_t*)&lo[row * Kp + 2 * c] = (uint32_t)l0 | ((uint32_t)l1 << 16);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_syrk_mfma(const uint16_t* __restrict__ hi, const uint16_t* __restrict__ lo,
+                                                   int64_t Kp, int64_t kchunk, int ntiles, float* __restrict__ partial)
+{
+    __shared__ __align__(16) uint16_t sAh[ST * SLD];
+    __shared__ __align__(16) uint16_t sAl[ST * SLD];
+    __shared__ __align__(16) uint16_t sBh[ST * SLD];
+    __shared__ __align__(16) uint16_t sBl[ST * SLD];
+    const int t = blockIdx.x;
+    int bi = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while (bi * (bi + 1) / 2 > t) --bi;
+    while ((bi + 1) * (bi + 2) / 2 <= t) ++bi;
+    const int bj = t - bi * (bi + 1) / 2;
+    const int split = blockIdx.y;
+    const int64_t kb = (int64_t)split * kchunk;
+    const int64_t ke = min(kb + kchunk, Kp);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wy = wave >> 1, wx = wave & 1;
+    const uint16_t* Ah = hi + (int64_t)bi * ST * Kp;
+    const uint16_t* Al = lo + (int64_t)bi * ST * Kp;
+    const uint16_t* Bh = hi + (int64_t)bj * ST * Kp;
+    const uint16_t* Bl = lo + (int64_t)bj * ST * Kp;
+    f32x16 acc[2][2];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
+    for (int64_t k0 = kb; k0 < ke; k0 += SK) {
+        // 128 rows x 32 bf16 = 512 chunks of 16 B per array
+        for (int pass = 0; pass < 2; ++pass) {
+            const int idx = pass * 256 + tid;
+            const int row = idx >> 2, ch = idx & 3;
+            const int64_t go = (int64_t)row * Kp + k0 + ch * 8;
+            const int lo_ = row * SLD + ch * 8;
+            *(uint4*)&sAh[lo_] = *(const uint4*)&Ah[go];
+            *(uint4*)&sAl[lo_] = *(const uint4*)&Al[go];
+            *(uint4*)&sBh[lo_] = *(const uint4*)&Bh[go];
+            *(uint4*)&sBl[lo_] = *(const uint4*)&Bl[go];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < SK; ks += 16) {
+            bf16x8 fah[2], fal[2], fbh[2], fbl[2];
+            const int kof = ks + 8 * (lane >> 5);
+            for (int a = 0; a < 2; ++a) {
+                const int r = wy * 64 + a * 32 + (lane & 31);
+                fah[a] = *(const bf16x8*)&sAh[r * SLD + kof];
+                fal[a] = *(const bf16x8*)&sAl[r * SLD + kof];
+            }
+            for (int b = 0; b < 2; ++b) {
+                const int c = wx * 64 + b * 32 + (lane & 31);
+                fbh[b] = *(const bf16x8*)&sBh[c * SLD + kof];
+                fbl[b] = *(const bf16x8*)&sBl[c * SLD + kof];
+            }
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b) {
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[a], fbh[b], acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[a], fbl[b], acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fal[a], fbh[b], acc[a][b], 0, 0, 0);
+                }
+        }
+        __syncthreads();
+    }
+    float* P = partial + ((int64_t)split * ntiles + t) * ST * ST;
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int r = 0; r < 16; ++r) {
+                const int i = wy * 64 + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const int j = wx * 64 + b * 32 + (lane & 31);
+                P[i * ST + j] = acc[a][b][r];
+            }
+}
+
+__global__ void k_syrk_reduce(const float* __restrict__ partial, int nsplit, int ntiles, int D, float* __restrict__ cov)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)D * D) return;
+    int i = (int)(idx / D), j = (int)(idx - (int64_t)i * D);
+    if (i < j) { int x = i; i = j; j = x; }
+    const int bi = i / ST, bj = j / ST;
+    const int t = bi * (bi + 1) / 2 + bj;
+    const int64_t off = (int64_t)t * ST * ST + (i - bi * ST) * ST + (j - bj * ST);
+    float s = 0.f;
+    for (int q = 0; q < nsplit; ++q) s += partial[(int64_t)q * ntiles * ST * ST + off];
+    cov[idx] = s;
+}
+
+// ------------------------------------------------------------------------------- launchers
+static SortedCutoffs sort_cutoffs(const Cutoffs& c)
+{
+    SortedCutoffs s;
+    s.n = c.n;
+    for (int i = 0; i < c.n; ++i) { s.N[i] = c.N[i]; s.slot[i] = i; }
+    for (int i = 1; i < c.n; ++i)
+        for (int j = i; j > 0 && s.N[j - 1] > s.N[j]; --j) {
+            int a = s.N[j]; s.N[j] = s.N[j - 1]; s.N[j - 1] = a;
+            int b = s.slot[j]; s.slot[j] = s.slot[j - 1]; s.slot[j - 1] = b;
+        }
+    return s;
+}
+
+hipError_t launch_cov_small(int prec, int32_t G, int32_t D, const void* coef, int64_t ldc, int32_t Nmax,
+                            const Cutoffs& cut, int basis, void* cov, hipStream_t st)
+{
+    SortedCutoffs sc = sort_cutoffs(cut);
+    const int npairs = D * (D + 1) / 2;
+    const int threads = ((npairs + 63) / 64) * 64;
+    const size_t lds = (size_t)D * 64 * sizeof(double2);
+    prof_begin("k_cov_small", st);
+    if (prec == MM_MIXED)
+        hipLaunchKernelGGL((k_cov_small<float2, float>), dim3(G), dim3(threads), lds, st, D, (const float2*)coef, ldc,
+                           Nmax, sc, basis, G, (float*)cov);
+    else
+        hipLaunchKernelGGL((k_cov_small<double2, double>), dim3(G), dim3(threads), lds, st, D, (const double2*)coef,
+                           ldc, Nmax, sc, basis, G, (double*)cov);
+    prof_end("k_cov_small", st);
+    return hipGetLastError();
+}
+
+hipError_t launch_corr(int prec, int64_t mats, int32_t D, const void* cov, void* corr, hipStream_t st)
+{
+    const int64_t total = mats * D * D;
+    if (total == 0) return hipSuccess;
+    const int blocks = (int)((total + 255) / 256);
+    prof_begin("k_corr", st);
+    if (prec == MM_MIXED)
+        hipLaunchKernelGGL(k_corr<float>, dim3(blocks), dim3(256), 0, st, total, D, (const float*)cov, (float*)corr);
+    else
+        hipLaunchKernelGGL(k_corr<double>, dim3(blocks), dim3(256), 0, st, total, D, (const double*)cov,
+                           (double*)corr);
+    prof_end("k_corr", st);
+    return hipGetLastError();
+}
+
+hipError_t launch_cov_fp64(int32_t G, int32_t D, const void* coef, int64_t ldc, int32_t N, int basis, void* cov,
+                           hipStream_t st)
+{
+    const int tn = (D + F64T - 1) / F64T;
+    const int ntiles = tn * (tn + 1) / 2;
+    for (int g = 0; g < G; ++g) {
+        prof_begin("k_cov_fp64", st);
+        hipLaunchKernelGGL(k_cov_fp64, dim3(ntiles), dim3(256), 0, st, D,
+                           (const double2*)coef + (int64_t)g * D * ldc, ldc, N, basis,
+                           (double*)cov + (int64_t)g * D * D);
+        prof_end("k_cov_fp64", st);
+    }
+    return hipGetLastError();
+}
+
+struct MfmaShape {
+    int tn, ntiles, nsplit;
+    int64_t Dp, Kp, kchunk;
+    size_t hi, lo, partial, total;
+};
+
+static MfmaShape mfma_shape(int32_t D, int32_t N)
+{
+    MfmaShape s;
+    s.tn = (D + ST - 1) / ST;
+    s.ntiles = s.tn * (s.tn + 1) / 2;
+    s.Dp = (int64_t)s.tn * ST;
+    s.Kp = ((2ll * (N + 1) + SK - 1) / SK) * SK;
+    // enough workgroups to cover the chip a few times, each with >= 8 k-stages
+    int want = (1024 + s.ntiles - 1) / s.ntiles;
+    int64_t maxsplit = s.Kp / (8 * SK);
+    if (maxsplit < 1) maxsplit = 1;
+    s.nsplit = (int)std::min<int64_t>(want, maxsplit);
+    if (s.nsplit > 65535) s.nsplit = 65535;
+    int64_t per = (s.Kp + s.nsplit - 1) / s.nsplit;
+    s.kchunk = ((per + SK - 1) / SK) * SK;
+    s.nsplit = (int)((s.Kp + s.kchunk - 1) / s.kchunk);
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    size_t o = 0;
+    s.hi = o; o += al((size_t)s.Dp * s.Kp * 2);
+    s.lo = o; o += al((size_t)s.Dp * s.Kp * 2);
+    s.partial = o; o += al((size_t)s.nsplit * s.ntiles * ST * ST * 4);
+    s.total = o;
+    return s;
+}
+
+size_t cov_mfma_workspace(int32_t G, int32_t D, int32_t Nmax)
+{
+    (void)G;
+    return mfma_shape(D, Nmax).total;
+}
+
+hipError_t launch_cov_mfma(int32_t G, int32_t D, const void* coef, int64_t ldc, int32_t N, int basis, void* cov,
+                           char* ws, hipStream_t st)
+{
+    MfmaShape s = mfma_shape(D, N);
+    uint16_t* hi = (uint16_t*)(ws + s.hi);
+    uint16_t* lo = (uint16_t*)(ws + s.lo);
+    float* part = (float*)(ws + s.partial);
+    for (int g = 0; g < G; ++g) {
+        const float2* cg = (const float2*)coef + (int64_t)g * D * ldc;
+        int bx = (int)std::min<int64_t>((s.Kp / 2 + 255) / 256, 64);
+        prof_begin("k_split_bf16", st);
+        hipLaunchKernelGGL(k_split_bf16, dim3(bx, s.Dp), dim3(256), 0, st, D, (int)s.Dp, cg, ldc, N, basis, s.Kp, hi, lo);
+        prof_end("k_split_bf16", st);
+        prof_begin("k_syrk_mfma", st);
+        hipLaunchKernelGGL(k_syrk_mfma, dim3(s.ntiles, s.nsplit), dim3(256), 0, st, hi, lo, s.Kp, s.kchunk, s.ntiles,
+                           part);
+        prof_end("k_syrk_mfma", st);
+        const int64_t tot = (int64_t)D * D;
+        prof_begin("k_syrk_reduce", st);
+        hipLaunchKernelGGL(k_syrk_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, part, s.nsplit,
+                           s.ntiles, D, (float*)cov + (int64_t)g * D * D);
+        prof_end("k_syrk_reduce", st);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace mm

@@ -1,0 +1,111 @@
+// Internal declarations shared by the host runtime (mm_api.cpp, mm_plan.cpp)
+// and the gfx950 kernels (mm_nufft.hip, mm_cov.hip).  Not part of the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "mm.h"
+
+namespace mm {
+
+constexpr int kMaxStages = 12;     // radix stages of one in-LDS sub-FFT
+constexpr int kMaxSub = 2048;      // longest in-LDS sub-FFT
+constexpr int kMaxTaps = 40;       // spreading taps per event
+constexpr int kMaxCutoffs = 128;   // cutoffs per mm_cov call
+constexpr int kGLNodes = 64;       // positive nodes of the 128-point Gauss-Legendre rule
+
+// Exact unsigned division a / d for a < 2^22, d < 2^20: (a * M) >> 42, M = ceil(2^42/d).
+struct FastDiv {
+    uint64_t M;
+    uint32_t d;
+};
+
+// One in-place decimation-in-frequency FFT of length n held in LDS.
+struct FFTDesc {
+    int n;
+    int ns;                   // number of radix stages
+    int r[kMaxStages];        // radix of stage s (2, 3, 4 or 5)
+    int m[kMaxStages];        // span / radix of stage s
+    int tws[kMaxStages];      // twiddle-table stride n / span of stage s
+    FastDiv dm[kMaxStages];   // division by m[s]
+    FastDiv dnr[kMaxStages];  // division by n / r[s]
+};
+
+// Averaging-kernel parameters in grid units (x = cell distance).
+struct KernParams {
+    int kind;        // MM_GAUSSIAN / MM_KAISER_BESSEL / MM_ES
+    int w;           // taps per event
+    double hw;       // w / 2: first tap sits at floor(g - hw) + 1
+    // ES: exp(beta (sqrt(1 - (x/hw)^2) - 1))
+    double es_beta, es_inv_hw;
+    // Gaussian: exp(-t1 x^2), t1 = pi / lambda; FGG tables e3[k] = exp(-t1 k^2)
+    double g_t1, g_lambda;
+    int g_msp;
+    double g_e3[kMaxTaps / 2 + 1];
+    // Kaiser-Bessel: inv_norm * sinh(b s)/s, s = sqrt(m^2 - x^2) (sin branch outside)
+    double kb_b, kb_m, kb_inv_norm;
+};
+
+struct Plan {
+    int prec;            // mm_prec
+    int kernel;          // mm_kernel
+    int N, M;            // cutoff and M = 2N + 1
+    double tol, sigma;
+    int msp;             // spreading half-width rule value M_sp
+    int Mr, L, L1, L2;   // real grid length, complex length Mr/2 = L1 * L2
+    KernParams kp;
+    FFTDesc F1, F2;
+    int CB;              // columns per block of the column pass
+    int R;               // row pairs per block of the row pass
+    int tile;            // cells per spreading tile
+    int fused;           // 1: single-workgroup LDS-resident NUFFT per series
+    int fused_threads;
+};
+
+// Plan construction (host only, no device calls).  Returns MM_OK or an error.
+mm_status make_plan(int32_t N, mm_kernel kernel, double tol, mm_prec prec, const mm_tuning* tune, Plan* p);
+uint64_t smooth_even_at_least(uint64_t n);
+FastDiv make_fastdiv(uint32_t d);
+void gauss_legendre_pos(int n_pos, double* x, double* w);   // nodes/weights on (0,1] of a 2n_pos rule on [-1,1]
+
+// Workspace layout of one mm_nufft1 call.
+struct NufftWs {
+    size_t tw1, tw2, twL, twM, rev1, pos2, dfac, flag, grid, total;
+    int S_grid;   // series whose grids are resident at once
+};
+NufftWs nufft_workspace(const Plan& p, int32_t S);
+
+// Launchers (mm_nufft.hip).  All asynchronous on `st`.
+hipError_t ensure_constants(int device);
+hipError_t launch_prep(const Plan& p, const NufftWs& w, char* ws, hipStream_t st);
+hipError_t launch_validate(int32_t S, const int64_t* offsets, const double* t, const void* dp, int dp_fp64,
+                           double t0, double T, int* flag, hipStream_t st);
+hipError_t launch_nufft_tiled(const Plan& p, const NufftWs& w, char* ws, int32_t s_begin, int32_t s_count,
+                              const int64_t* offsets, const double* t, const void* dp, int dp_fp64,
+                              double t0, double T, void* coef, int64_t ldc, hipStream_t st);
+hipError_t launch_nufft_fused(const Plan& p, const NufftWs& w, char* ws, int32_t S, const int64_t* offsets,
+                              const double* t, const void* dp, int dp_fp64, double t0, double T,
+                              void* coef, int64_t ldc, hipStream_t st);
+
+// Contraction launchers (mm_cov.hip).
+struct Cutoffs {
+    int n;
+    int N[kMaxCutoffs];
+};
+hipError_t launch_cov_small(int prec, int32_t G, int32_t D, const void* coef, int64_t ldc, int32_t Nmax,
+                            const Cutoffs& cut, int basis, void* cov, hipStream_t st);
+hipError_t launch_corr(int prec, int64_t mats, int32_t D, const void* cov, void* corr, hipStream_t st);
+size_t cov_mfma_workspace(int32_t G, int32_t D, int32_t Nmax);
+hipError_t launch_cov_mfma(int32_t G, int32_t D, const void* coef, int64_t ldc, int32_t N, int basis,
+                           void* cov, char* ws, hipStream_t st);
+hipError_t launch_cov_fp64(int32_t G, int32_t D, const void* coef, int64_t ldc, int32_t N, int basis,
+                           void* cov, hipStream_t st);
+
+// Optional per-kernel timing with HIP events on the launch stream.
+void prof_begin(const char* name, hipStream_t st);
+void prof_end(const char* name, hipStream_t st);
+
+}  // namespace mm

@@ -1,0 +1,601 @@
+// gfx950 kernels of the type-1 NUFFT (Sec. 2.2.5 of the paper):
+//   k_prep      FP64 tables: FFT twiddles, digit-reversal maps, deconvolution
+//               factors 1/(2 pi psi_hat(k/Mr)) of the averaging kernel
+//   k_spread    spreading onto the periodic oversampled grid (Eq. Der:15), one
+//               workgroup per (series, grid tile), LDS accumulation, no global atomics
+//   k_fft_cols  first pass of the grid FFT (Eq. Der:16): length-L1 transforms of
+//               strided columns of the L1 x L2 view of the packed complex grid,
+//               times the four-step twiddle, in place
+//   k_fft_rows  second pass: length-L2 transforms of rows, the real-input
+//               untangling, deconvolution (Eq. Der:17) and the 1/2pi of the
+//               coefficient definition; writes c_k, k = 0..N
+//
+// The real grid x[0..Mr) is FFT'd as the complex sequence z_j = x_2j + i x_2j+1
+// of length L = Mr/2 = L1 L2; every sub-transform is an in-place mixed-radix
+// (4, 5, 3, 2) decimation-in-frequency FFT in LDS whose output sits in
+// digit-reversed positions.
+#include <hip/hip_runtime.h>
+
+#include "mm_internal.h"
+
+namespace mm {
+
+template <typename T> struct CT;
+template <> struct CT<float> { using type = float2; };
+template <> struct CT<double> { using type = double2; };
+
+__device__ __forceinline__ uint32_t fdiv(uint32_t a, const FastDiv& f)
+{
+    return (uint32_t)(((uint64_t)a * f.M) >> 42);
+}
+
+template <typename C> __device__ __forceinline__ C cadd(C a, C b) { return C{a.x + b.x, a.y + b.y}; }
+template <typename C> __device__ __forceinline__ C csub(C a, C b) { return C{a.x - b.x, a.y - b.y}; }
+template <typename C> __device__ __forceinline__ C cmul(C a, C b)
+{
+    return C{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename C, typename T> __device__ __forceinline__ C cscale(C a, T s) { return C{a.x * s, a.y * s}; }
+// -i * a
+template <typename C> __device__ __forceinline__ C cmi(C a) { return C{a.y, -a.x}; }
+// +i * a
+template <typename C> __device__ __forceinline__ C cpi(C a) { return C{-a.y, a.x}; }
+
+// One radix-r butterfly of an in-place DIF stage: base[q*m], q < r, replaced by
+// their r-point DFT (exp(-2 pi i/r)), output q' times W_span^{j q'} = tw[j q' ts].
+template <typename T>
+__device__ __forceinline__ void butterfly(typename CT<T>::type* base, int m, int r, int j, int ts,
+                                          const typename CT<T>::type* tw)
+{
+    using C = typename CT<T>::type;
+    if (r == 4) {
+        C x0 = base[0], x1 = base[m], x2 = base[2 * m], x3 = base[3 * m];
+        C a = cadd(x0, x2), b = csub(x0, x2), c = cadd(x1, x3), d = csub(x1, x3);
+        C y0 = cadd(a, c), y2 = csub(a, c), y1 = cadd(b, cmi(d)), y3 = cadd(b, cpi(d));
+        if (j) {
+            y1 = cmul(y1, tw[j * ts]);
+            y2 = cmul(y2, tw[2 * j * ts]);
+            y3 = cmul(y3, tw[3 * j * ts]);
+        }
+        base[0] = y0; base[m] = y1; base[2 * m] = y2; base[3 * m] = y3;
+    } else if (r == 5) {
+        const T c1 = (T)0.30901699437494742410, c2 = (T)-0.80901699437494742410;
+        const T s1 = (T)0.95105651629515357212, s2 = (T)0.58778525229247312917;
+        C x0 = base[0], x1 = base[m], x2 = base[2 * m], x3 = base[3 * m], x4 = base[4 * m];
+        C a1 = cadd(x1, x4), b1 = csub(x1, x4), a2 = cadd(x2, x3), b2 = csub(x2, x3);
+        C y0 = cadd(x0, cadd(a1, a2));
+        C p1 = C{x0.x + c1 * a1.x + c2 * a2.x, x0.y + c1 * a1.y + c2 * a2.y};
+        C q1 = C{s1 * b1.x + s2 * b2.x, s1 * b1.y + s2 * b2.y};
+        C p2 = C{x0.x + c2 * a1.x + c1 * a2.x, x0.y + c2 * a1.y + c1 * a2.y};
+        C q2 = C{s2 * b1.x - s1 * b2.x, s2 * b1.y - s1 * b2.y};
+        C y1 = cadd(p1, cmi(q1)), y4 = cadd(p1, cpi(q1));
+        C y2 = cadd(p2, cmi(q2)), y3 = cadd(p2, cpi(q2));
+        if (j) {
+            y1 = cmul(y1, tw[j * ts]);
+            y2 = cmul(y2, tw[2 * j * ts]);
+            y3 = cmul(y3, tw[3 * j * ts]);
+            y4 = cmul(y4, tw[4 * j * ts]);
+        }
+        base[0] = y0; base[m] = y1; base[2 * m] = y2; base[3 * m] = y3; base[4 * m] = y4;
+    } else if (r == 3) {
+        const T s3 = (T)0.86602540378443864676;
+        C x0 = base[0], x1 = base[m], x2 = base[2 * m];
+        C t1 = cadd(x1, x2);
+        C t2 = C{x0.x - (T)0.5 * t1.x, x0.y - (T)0.5 * t1.y};
+        C t3 = cscale(csub(x1, x2), s3);
+        C y0 = cadd(x0, t1), y1 = cadd(t2, cmi(t3)), y2 = cadd(t2, cpi(t3));
+        if (j) {
+            y1 = cmul(y1, tw[j * ts]);
+            y2 = cmul(y2, tw[2 * j * ts]);
+        }
+        base[0] = y0; base[m] = y1; base[2 * m] = y2;
+    } else {
+        C x0 = base[0], x1 = base[m];
+        C y1 = csub(x0, x1);
+        if (j) y1 = cmul(y1, tw[j * ts]);
+        base[0] = cadd(x0, x1); base[m] = y1;
+    }
+}
+
+// nb independent length-n transforms, transform b at buf + b*ldb (unit stride).
+// tw holds W_n^j = exp(-2 pi i j/n), j < n.  Ends with a barrier.
+template <typename T>
+__device__ void fft_lds(typename CT<T>::type* buf, int ldb, int nb, const FFTDesc& F,
+                        const typename CT<T>::type* tw)
+{
+    for (int s = 0; s < F.ns; ++s) {
+        const int r = F.r[s], m = F.m[s], ts = F.tws[s];
+        const int nr = (int)F.dnr[s].d, len = m * r;
+        const int total = nb * nr;
+        for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+            int b = (int)fdiv((uint32_t)idx, F.dnr[s]);
+            int bf = idx - b * nr;
+            int blk = (int)fdiv((uint32_t)bf, F.dm[s]);
+            int j = bf - blk * m;
+            butterfly<T>(buf + b * ldb + blk * len + j, m, r, j, ts, tw);
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Time -> grid reduction (FP64).  u = (t - t0)/(T - t0); g = u Mr formed exactly as
+// p + e (two-product); first tap l0 = floor(g - hw) + 1 and fraction f = frac(g - hw),
+// so tap j sits at cell l0 + j at kernel argument x_j = j + 1 - f - hw in (-hw, hw].
+// The key l0 is nondecreasing in t, which the per-tile binary searches rely on.
+template <bool EXACT_DIV>
+__device__ __forceinline__ void cell_of(double t, double t0, double span, double inv_span, int Mr, double hw,
+                                        int64_t& l0, double& f)
+{
+    double u = EXACT_DIV ? (t - t0) / span : (t - t0) * inv_span;
+    double p = u * (double)Mr;
+    double e = fma(u, (double)Mr, -p);
+    double tt = p - hw;
+    double fl = floor(tt);
+    double fr = (tt - fl) + e;
+    if (fr < 0.0) { fl -= 1.0; fr += 1.0; }
+    if (fr >= 1.0) { fl += 1.0; fr -= 1.0; }
+    l0 = (int64_t)fl + 1;
+    f = fr;
+}
+
+__device__ __forceinline__ float fexp2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+// Add the w taps of one event (strength v, fraction f) to acc[base + j], j < w,
+// keeping only cells inside [0, len).
+template <typename T, int KIND>
+__device__ __forceinline__ void spread_event(T* acc, int len, int base, double f, T v, const KernParams& kp)
+{
+    const int w = kp.w;
+    if (KIND == MM_ES) {
+        // phi(x) = exp(beta (sqrt(1 - (x/hw)^2) - 1)), |x| <= hw (Eq. Der:10 rescaled to w cells)
+        const T x0 = (T)(1.0 - f - kp.hw);
+        const T inv = (T)kp.es_inv_hw;
+        if constexpr (sizeof(T) == 4) {
+            const float b2 = (float)(kp.es_beta * 1.4426950408889634074);
+            for (int j = 0; j < w; ++j) {
+                int pos = base + j;
+                if ((unsigned)pos < (unsigned)len) {
+                    float z = (x0 + (float)j) * inv;
+                    float s = fsqrt(fmaxf(1.0f - z * z, 0.0f));
+                    atomicAdd(&acc[pos], v * fexp2(b2 * (s - 1.0f)));
+                }
+            }
+        } else {
+            const double beta = kp.es_beta;
+            for (int j = 0; j < w; ++j) {
+                int pos = base + j;
+                if ((unsigned)pos < (unsigned)len) {
+                    double z = (x0 + (double)j) * inv;
+                    double s = sqrt(fmax(1.0 - z * z, 0.0));
+                    atomicAdd(&acc[pos], v * exp(beta * (s - 1.0)));
+                }
+            }
+        }
+    } else if (KIND == MM_GAUSSIAN) {
+        // Fast Gaussian gridding (Eq. Der:20): phi(k - f) = E1 E2^k E3_k with
+        // E1 = exp(-t1 f^2), E2 = exp(2 t1 f), E3_k = exp(-t1 k^2); taps k = -(msp-1)..msp.
+        const int msp = kp.g_msp;
+        const T t1 = (T)kp.g_t1;
+        const T ff = (T)f;
+        const T E1 = exp(-t1 * ff * ff);
+        const T E2 = exp((T)2 * t1 * ff);
+        const int jc = base + msp - 1;            // cell of k = 0
+        if ((unsigned)jc < (unsigned)len) atomicAdd(&acc[jc], v * E1);
+        T p = E1;
+        for (int k = 1; k <= msp; ++k) {
+            p *= E2;
+            int pos = jc + k;
+            if ((unsigned)pos < (unsigned)len) atomicAdd(&acc[pos], v * (p * (T)kp.g_e3[k]));
+        }
+        const T iE2 = (T)1 / E2;
+        p = E1;
+        for (int k = 1; k < msp; ++k) {
+            p *= iE2;
+            int pos = jc - k;
+            if ((unsigned)pos < (unsigned)len) atomicAdd(&acc[pos], v * (p * (T)kp.g_e3[k]));
+        }
+    } else {
+        // Kaiser-Bessel (Eq. Der:8 in cells): inv_norm sinh(b s)/s, s = sqrt(m^2 - x^2),
+        // continued by sin(b s')/s', s' = sqrt(x^2 - m^2), outside |x| <= m.
+        const T x0 = (T)(1.0 - f - kp.hw);
+        const T m2 = (T)(kp.kb_m * kp.kb_m), b = (T)kp.kb_b, inv_norm = (T)kp.kb_inv_norm;
+        for (int j = 0; j < w; ++j) {
+            int pos = base + j;
+            if ((unsigned)pos >= (unsigned)len) continue;
+            T x = x0 + (T)j;
+            T s2 = m2 - x * x;
+            T val;
+            if (s2 > (T)0) {
+                T s = sqrt(s2);
+                T a = b * s;
+                if constexpr (sizeof(T) == 4) {
+                    if (a < 0.5f) {
+                        float a2 = a * a;
+                        val = b * (1.0f + a2 * (1.0f / 6 + a2 * (1.0f / 120 + a2 * (1.0f / 5040))));
+                    } else {
+                        float E = expf(a);
+                        val = (E - 1.0f / E) / (2.0f * s);
+                    }
+                } else {
+                    val = sinh(a) / s;
+                }
+            } else if (s2 < (T)0) {
+                T s = sqrt(-s2);
+                val = sin(b * s) / s;
+            } else {
+                val = b;
+            }
+            atomicAdd(&acc[pos], v * (val * inv_norm));
+        }
+    }
+}
+
+template <typename T, typename DPT, int KIND, bool EXACT_DIV>
+__global__ __launch_bounds__(256) void k_spread(const int64_t* __restrict__ offsets, const double* __restrict__ t,
+                                                const DPT* __restrict__ dp, int s_begin, double t0, double span,
+                                                double inv_span, KernParams kp, int Mr, int tile,
+                                                T* __restrict__ grid, int64_t grid_stride)
+{
+    extern __shared__ __align__(16) char smem_raw[];
+    T* acc = reinterpret_cast<T*>(smem_raw);
+    __shared__ int64_t rng[6];
+    const int s = s_begin + blockIdx.y;
+    const int a = blockIdx.x * tile;
+    const int len = min(tile, Mr - a);
+    for (int i = threadIdx.x; i < len; i += blockDim.x) acc[i] = (T)0;
+    const int64_t e0 = offsets[s], e1 = offsets[s + 1];
+    if (threadIdx.x < 6) {
+        // Events whose taps [l0, l0 + w) meet cells [a, a + len) + m Mr, m = -1, 0, 1:
+        // keys in [a + m Mr - w + 1, a + len + m Mr).
+        const int64_t m = (int64_t)(threadIdx.x >> 1) - 1;
+        const int64_t key = (threadIdx.x & 1) ? (int64_t)a + len + m * Mr : (int64_t)a + m * Mr - kp.w + 1;
+        int64_t lo = e0, hi = e1;
+        while (lo < hi) {
+            int64_t mid = (lo + hi) >> 1;
+            int64_t l0;
+            double f;
+            cell_of<EXACT_DIV>(t[mid], t0, span, inv_span, Mr, kp.hw, l0, f);
+            if (l0 < key) lo = mid + 1;
+            else hi = mid;
+        }
+        rng[threadIdx.x] = lo;
+    }
+    __syncthreads();
+    for (int mi = 0; mi < 3; ++mi) {
+        const int64_t b0 = rng[2 * mi], b1 = rng[2 * mi + 1];
+        const int64_t shift = (int64_t)a + (int64_t)(mi - 1) * Mr;
+        for (int64_t i = b0 + threadIdx.x; i < b1; i += blockDim.x) {
+            int64_t l0;
+            double f;
+            cell_of<EXACT_DIV>(t[i], t0, span, inv_span, Mr, kp.hw, l0, f);
+            spread_event<T, KIND>(acc, len, (int)(l0 - shift), f, (T)dp[i], kp);
+        }
+    }
+    __syncthreads();
+    T* out = grid + (int64_t)blockIdx.y * grid_stride + a;
+    for (int i = threadIdx.x; i < len; i += blockDim.x) out[i] = acc[i];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_fft_cols(T* __restrict__ grid, int64_t grid_stride, int L1, int L2,
+                                                  int cb_shift, FFTDesc F1, const typename CT<T>::type* __restrict__ tw1,
+                                                  const typename CT<T>::type* __restrict__ twL,
+                                                  const int* __restrict__ rev1)
+{
+    using C = typename CT<T>::type;
+    extern __shared__ __align__(16) char smem_raw[];
+    C* tws = reinterpret_cast<C*>(smem_raw);
+    C* buf = tws + L1;
+    const int CB = 1 << cb_shift;
+    const int ldb = L1 | 1;
+    C* z = reinterpret_cast<C*>(grid + (int64_t)blockIdx.y * grid_stride);
+    const int c0 = blockIdx.x * CB;
+    const int nb = min(CB, L2 - c0);
+    for (int i = threadIdx.x; i < L1; i += blockDim.x) tws[i] = tw1[i];
+    for (int idx = threadIdx.x; idx < L1 * CB; idx += blockDim.x) {
+        int l1 = idx >> cb_shift, b = idx & (CB - 1);
+        if (b < nb) buf[b * ldb + l1] = z[(int64_t)l1 * L2 + c0 + b];
+    }
+    __syncthreads();
+    fft_lds<T>(buf, ldb, nb, F1, tws);
+    for (int idx = threadIdx.x; idx < L1 * CB; idx += blockDim.x) {
+        int p = idx >> cb_shift, b = idx & (CB - 1);
+        if (b < nb) {
+            int k1 = rev1[p];
+            C v = cmul(buf[b * ldb + p], twL[(int64_t)(c0 + b) * k1]);
+            z[(int64_t)k1 * L2 + c0 + b] = v;
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_fft_rows(const T* __restrict__ grid, int64_t grid_stride, int L1, int L2,
+                                                  int r_shift, FFTDesc F2, const typename CT<T>::type* __restrict__ tw2,
+                                                  const int* __restrict__ pos2, const typename CT<T>::type* __restrict__ twM,
+                                                  const T* __restrict__ dfac, int N, typename CT<T>::type* __restrict__ coef,
+                                                  int64_t ldc, int s_out)
+{
+    using C = typename CT<T>::type;
+    extern __shared__ __align__(16) char smem_raw[];
+    C* tws = reinterpret_cast<C*>(smem_raw);
+    C* buf = tws + L2;
+    const int R = 1 << r_shift;
+    const int ldb = L2 | 1;
+    const C* Y = reinterpret_cast<const C*>(grid + (int64_t)blockIdx.y * grid_stride);
+    C* out = coef + (int64_t)(s_out + blockIdx.y) * ldc;
+    const int P = L1 / 2 + 1;
+    const int p0 = blockIdx.x * R;
+    const int nr = min(R, P - p0);
+    for (int i = threadIdx.x; i < L2; i += blockDim.x) tws[i] = tw2[i];
+    // LDS row 2i holds matrix row p0+i, row 2i+1 its mirror (L1 - p0 - i) mod L1.
+    for (int i = 0; i < 2 * nr; ++i) {
+        const int p = p0 + (i >> 1);
+        const int k1 = (i & 1) ? (L1 - p) % L1 : p;
+        const C* src = Y + (int64_t)k1 * L2;
+        for (int j = threadIdx.x; j < L2; j += blockDim.x) buf[i * ldb + j] = src[j];
+    }
+    __syncthreads();
+    fft_lds<T>(buf, ldb, 2 * nr, F2, tws);
+    const int total = 2 * R * L2;
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+        const int i = idx & (R - 1);
+        const int t2 = idx >> r_shift;
+        const int side = t2 & 1, k2 = t2 >> 1;
+        if (i >= nr) continue;
+        const int p = p0 + i;
+        const int rowA = p, rowB = (L1 - p) % L1;
+        if (side && rowB == rowA) continue;
+        const int k1 = side ? rowB : rowA;
+        const int64_t k = (int64_t)k1 + (int64_t)L1 * k2;
+        if (k > N) continue;
+        const int k2m = (k1 == 0) ? (k2 == 0 ? 0 : L2 - k2) : (L2 - 1 - k2);
+        const C Zk = buf[(2 * i + side) * ldb + pos2[k2]];
+        const C Zm = buf[(2 * i + 1 - side) * ldb + pos2[k2m]];
+        // X_k = (Z_k + conj Z_{L-k})/2 - (i/2) W_Mr^k (Z_k - conj Z_{L-k})
+        const C A = C{Zk.x + Zm.x, Zk.y - Zm.y};
+        const C B = C{Zk.x - Zm.x, Zk.y + Zm.y};
+        const C WB = cmul(twM[k], B);
+        const T d = dfac[k] * (T)0.5;
+        out[k] = C{(A.x + WB.y) * d, (A.y - WB.x) * d};
+    }
+}
+
+struct GLRule {
+    double x[kGLNodes], w[kGLNodes];
+};
+
+// Modified Bessel function I0 by its power series sum_j (x^2/4)^j / (j!)^2.
+__device__ double bessel_i0(double x)
+{
+    double q = 0.25 * x * x, term = 1.0, sum = 1.0;
+    for (int j = 1; j < 1000; ++j) {
+        term *= q / ((double)j * (double)j);
+        sum += term;
+        if (term < 1e-17 * sum) break;
+    }
+    return sum;
+}
+
+// 1/(2 pi psi_hat(nu)) at nu = k/Mr for the kernel in grid units.
+__device__ double deconv_factor(const KernParams& kp, int k, int Mr, const GLRule& gl)
+{
+    const double pi = 3.14159265358979323846;
+    const double nu = (double)k / (double)Mr;
+    double ph;
+    if (kp.kind == MM_GAUSSIAN) {
+        ph = sqrt(kp.g_lambda) * exp(-pi * kp.g_lambda * nu * nu);
+    } else if (kp.kind == MM_KAISER_BESSEL) {
+        double a = kp.kb_b * kp.kb_b - (2.0 * pi * nu) * (2.0 * pi * nu);
+        ph = pi * kp.kb_inv_norm * bessel_i0(kp.kb_m * sqrt(fmax(a, 0.0)));   // Eq. Der:9 in cells
+    } else {
+        // hw int_{-1}^{1} exp(beta (sqrt(1 - z^2) - 1)) cos(2 pi nu hw z) dz by Gauss-Legendre (Eq. Der:11)
+        double acc = 0.0;
+        for (int q = 0; q < kGLNodes; ++q) {
+            double z = gl.x[q];
+            double phi = exp(kp.es_beta * (sqrt(1.0 - z * z) - 1.0));
+            acc += gl.w[q] * phi * cospi(2.0 * nu * kp.hw * z);
+        }
+        ph = 2.0 * kp.hw * acc;
+    }
+    return 1.0 / (2.0 * pi * ph);
+}
+
+__device__ int digit_rev(int p, const FFTDesc& F)
+{
+    int k = 0, mult = 1, rem = p;
+    for (int s = 0; s < F.ns; ++s) {
+        int q = rem / F.m[s];
+        rem -= q * F.m[s];
+        k += q * mult;
+        mult *= F.r[s];
+    }
+    return k;
+}
+
+__device__ int digit_pos(int k, const FFTDesc& F)
+{
+    int p = 0;
+    for (int s = 0; s < F.ns; ++s) {
+        int q = k % F.r[s];
+        k /= F.r[s];
+        p += q * F.m[s];
+    }
+    return p;
+}
+
+template <typename T>
+__global__ void k_prep(int L1, int L2, int L, int Mr, int N, KernParams kp, FFTDesc F1, FFTDesc F2, GLRule gl,
+                       typename CT<T>::type* tw1, typename CT<T>::type* tw2, typename CT<T>::type* twL,
+                       typename CT<T>::type* twM, int* rev1, int* pos2, T* dfac)
+{
+    using C = typename CT<T>::type;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    auto tw = [](int64_t j, int64_t n) {
+        double s, c;
+        sincospi(2.0 * (double)j / (double)n, &s, &c);
+        return C{(T)c, (T)-s};
+    };
+    if (i < L1) { tw1[i] = tw(i, L1); return; }
+    i -= L1;
+    if (i < L2) { tw2[i] = tw(i, L2); return; }
+    i -= L2;
+    if (i < L) { twL[i] = tw(i, L); return; }
+    i -= L;
+    if (i < L) { twM[i] = tw(i, Mr); return; }
+    i -= L;
+    if (i < L1) { rev1[i] = digit_rev((int)i, F1); return; }
+    i -= L1;
+    if (i < L2) { pos2[i] = digit_pos((int)i, F2); return; }
+    i -= L2;
+    if (i <= N) { dfac[i] = (T)deconv_factor(kp, (int)i, Mr, gl); return; }
+}
+
+__global__ void k_validate(int32_t S, const int64_t* __restrict__ offsets, const double* __restrict__ t,
+                           const void* __restrict__ dp, int dp_fp64, double t0, double T, int* flag)
+{
+    const int s = blockIdx.y;
+    const int64_t e0 = offsets[s], e1 = offsets[s + 1];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (s == 0 && e0 != 0) atomicOr(flag, 1);
+        if (e1 < e0) atomicOr(flag, 1);
+    }
+    if (e1 < e0) return;
+    int bad = 0;
+    for (int64_t i = e0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < e1;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double ti = t[i];
+        double di = dp_fp64 ? ((const double*)dp)[i] : (double)((const float*)dp)[i];
+        if (!isfinite(ti) || !(ti >= t0) || !(ti <= T)) bad |= 2;
+        if (!isfinite(di)) bad |= 4;
+        if (i > e0 && !(t[i - 1] <= ti)) bad |= 8;
+    }
+    if (bad) atomicOr(flag, bad);
+}
+
+static GLRule host_gl()
+{
+    static GLRule g;
+    static bool done = false;
+    if (!done) {
+        gauss_legendre_pos(kGLNodes, g.x, g.w);
+        done = true;
+    }
+    return g;
+}
+
+hipError_t ensure_constants(int) { return hipSuccess; }
+
+hipError_t launch_prep(const Plan& p, const NufftWs& w, char* ws, hipStream_t st)
+{
+    GLRule gl = host_gl();
+    int64_t total = 2ll * p.L1 + 2ll * p.L2 + 2ll * p.L + (p.N + 1);
+    int blocks = (int)((total + 255) / 256);
+    prof_begin("k_prep", st);
+    if (p.prec == MM_MIXED)
+        hipLaunchKernelGGL(k_prep<float>, dim3(blocks), dim3(256), 0, st, p.L1, p.L2, p.L, p.Mr, p.N, p.kp, p.F1,
+                           p.F2, gl, (float2*)(ws + w.tw1), (float2*)(ws + w.tw2), (float2*)(ws + w.twL),
+                           (float2*)(ws + w.twM), (int*)(ws + w.rev1), (int*)(ws + w.pos2), (float*)(ws + w.dfac));
+    else
+        hipLaunchKernelGGL(k_prep<double>, dim3(blocks), dim3(256), 0, st, p.L1, p.L2, p.L, p.Mr, p.N, p.kp, p.F1,
+                           p.F2, gl, (double2*)(ws + w.tw1), (double2*)(ws + w.tw2), (double2*)(ws + w.twL),
+                           (double2*)(ws + w.twM), (int*)(ws + w.rev1), (int*)(ws + w.pos2), (double*)(ws + w.dfac));
+    prof_end("k_prep", st);
+    return hipGetLastError();
+}
+
+hipError_t launch_validate(int32_t S, const int64_t* offsets, const double* t, const void* dp, int dp_fp64,
+                           double t0, double T, int* flag, hipStream_t st)
+{
+    if (S == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_validate, dim3(64, S), dim3(256), 0, st, S, offsets, t, dp, dp_fp64, t0, T, flag);
+    return hipGetLastError();
+}
+
+template <typename T, typename DPT, int KIND>
+static void launch_spread_t(const Plan& p, int s_begin, int s_count, const int64_t* offsets, const double* t,
+                            const DPT* dp, double t0, double t_end, T* grid, int64_t grid_stride, hipStream_t st)
+{
+    const int tiles = (p.Mr + p.tile - 1) / p.tile;
+    const size_t lds = (size_t)p.tile * sizeof(T);
+    const double span = t_end - t0;
+    if (p.prec == MM_PLAIN_FP64)
+        hipLaunchKernelGGL((k_spread<T, DPT, KIND, true>), dim3(tiles, s_count), dim3(256), lds, st, offsets, t, dp,
+                           s_begin, t0, span, 1.0 / span, p.kp, p.Mr, p.tile, grid, grid_stride);
+    else
+        hipLaunchKernelGGL((k_spread<T, DPT, KIND, false>), dim3(tiles, s_count), dim3(256), lds, st, offsets, t,
+                           dp, s_begin, t0, span, 1.0 / span, p.kp, p.Mr, p.tile, grid, grid_stride);
+}
+
+template <typename T, typename DPT>
+static void launch_spread_k(const Plan& p, int s_begin, int s_count, const int64_t* offsets, const double* t,
+                            const DPT* dp, double t0, double t_end, T* grid, int64_t grid_stride, hipStream_t st)
+{
+    if (p.kernel == MM_ES)
+        launch_spread_t<T, DPT, MM_ES>(p, s_begin, s_count, offsets, t, dp, t0, t_end, grid, grid_stride, st);
+    else if (p.kernel == MM_GAUSSIAN)
+        launch_spread_t<T, DPT, MM_GAUSSIAN>(p, s_begin, s_count, offsets, t, dp, t0, t_end, grid, grid_stride, st);
+    else
+        launch_spread_t<T, DPT, MM_KAISER_BESSEL>(p, s_begin, s_count, offsets, t, dp, t0, t_end, grid, grid_stride,
+                                                  st);
+}
+
+static int ilog2(int x)
+{
+    int s = 0;
+    while ((1 << s) < x) ++s;
+    return s;
+}
+
+template <typename T>
+static hipError_t nufft_tiled_t(const Plan& p, const NufftWs& w, char* ws, int32_t s_begin, int32_t s_count,
+                                const int64_t* offsets, const double* t, const void* dp, int dp_fp64, double t0,
+                                double T_, void* coef, int64_t ldc, hipStream_t st)
+{
+    using C = typename CT<T>::type;
+    T* grid = (T*)(ws + w.grid);
+    const int64_t gstride = p.Mr;
+    prof_begin("k_spread", st);
+    if (dp_fp64)
+        launch_spread_k<T, double>(p, s_begin, s_count, offsets, t, (const double*)dp, t0, T_, grid, gstride, st);
+    else
+        launch_spread_k<T, float>(p, s_begin, s_count, offsets, t, (const float*)dp, t0, T_, grid, gstride, st);
+    prof_end("k_spread", st);
+
+    const int cbs = ilog2(p.CB);
+    const size_t lds1 = (size_t)(p.L1 + p.CB * (p.L1 | 1)) * sizeof(C);
+    prof_begin("k_fft_cols", st);
+    hipLaunchKernelGGL(k_fft_cols<T>, dim3((p.L2 + p.CB - 1) / p.CB, s_count), dim3(256), lds1, st, grid, gstride,
+                       p.L1, p.L2, cbs, p.F1, (const C*)(ws + w.tw1), (const C*)(ws + w.twL),
+                       (const int*)(ws + w.rev1));
+    prof_end("k_fft_cols", st);
+
+    const int rs = ilog2(p.R);
+    const int P = p.L1 / 2 + 1;
+    const size_t lds2 = (size_t)(p.L2 + 2 * p.R * (p.L2 | 1)) * sizeof(C);
+    prof_begin("k_fft_rows", st);
+    hipLaunchKernelGGL(k_fft_rows<T>, dim3((P + p.R - 1) / p.R, s_count), dim3(256), lds2, st, grid, gstride, p.L1,
+                       p.L2, rs, p.F2, (const C*)(ws + w.tw2), (const int*)(ws + w.pos2), (const C*)(ws + w.twM),
+                       (const T*)(ws + w.dfac), p.N, (C*)coef, ldc, s_begin);
+    prof_end("k_fft_rows", st);
+    return hipGetLastError();
+}
+
+hipError_t launch_nufft_tiled(const Plan& p, const NufftWs& w, char* ws, int32_t s_begin, int32_t s_count,
+                              const int64_t* offsets, const double* t, const void* dp, int dp_fp64, double t0,
+                              double T, void* coef, int64_t ldc, hipStream_t st)
+{
+    if (s_count <= 0) return hipSuccess;
+    if (p.prec == MM_MIXED)
+        return nufft_tiled_t<float>(p, w, ws, s_begin, s_count, offsets, t, dp, dp_fp64, t0, T, coef, ldc, st);
+    return nufft_tiled_t<double>(p, w, ws, s_begin, s_count, offsets, t, dp, dp_fp64, t0, T, coef, ldc, st);
+}
+
+hipError_t launch_nufft_fused(const Plan&, const NufftWs&, char*, int32_t, const int64_t*, const double*,
+                              const void*, int, double, double, void*, int64_t, hipStream_t)
+{
+    return hipErrorNotSupported;
+}
+
+}  // namespace mm

@@ -1,0 +1,222 @@
+"""Python binding of libmm.so: argument marshalling only.
+
+Every step of the computation runs in the library's gfx950 kernels; this module
+checks tensor types, allocates outputs and workspace with PyTorch (device memory
+only) and passes raw pointers and the current HIP stream through the C ABI
+declared in ``include/mm.h``.  There is no fallback: without the built library
+every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmm.so")
+
+MM_OK, MM_ERR_ARG, MM_ERR_DATA, MM_ERR_TOL, MM_ERR_WORKSPACE, MM_ERR_HIP, MM_ERR_UNSUPPORTED = range(7)
+DIRICHLET, FEJER = 0, 1
+GAUSSIAN, KAISER_BESSEL, ES = 0, 1, 2
+PLAIN_FP64, MIXED = 0, 1
+
+_KERNELS = {"gaussian": GAUSSIAN, "g": GAUSSIAN, "fgg": GAUSSIAN, "kaiser_bessel": KAISER_BESSEL,
+            "kb": KAISER_BESSEL, "es": ES}
+_BASES = {"dirichlet": DIRICHLET, "fejer": FEJER}
+_PRECS = {"fp64": PLAIN_FP64, "plain": PLAIN_FP64, "mixed": MIXED}
+
+EXPORTED = ["mm_plan_query", "mm_nufft1_workspace_size", "mm_nufft1", "mm_cov_workspace_size", "mm_cov",
+            "mm_status_string", "mm_profile_enable", "mm_profile_read", "mm_profile_reset"]
+
+
+class MMError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__("%s failed: %s (status %d)" % (where, _status_text(status), status))
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("sigma", ctypes.c_double), ("tile", ctypes.c_int32),
+                ("fused", ctypes.c_int32), ("es_beta_per_tap", ctypes.c_double)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("width", ctypes.c_int32), ("msp", ctypes.c_int32), ("Mr", ctypes.c_int32),
+                ("L1", ctypes.c_int32), ("L2", ctypes.c_int32), ("fused", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("sigma", ctypes.c_double), ("beta", ctypes.c_double), ("tol", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libmm.so (after torch, so both share torch's HIP runtime)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libmm.so is not built; run `python -m paper_2003_02842_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i32, i64, f64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+        L.mm_plan_query.argtypes = [i32, i32, f64, i32, P, P]
+        L.mm_nufft1_workspace_size.argtypes = [i32, i32, i32, f64, i32, P, ctypes.POINTER(sz)]
+        L.mm_nufft1.argtypes = [i32, P, P, P, i32, f64, f64, i32, i32, f64, i32, P, P, i64, P, sz, i32, P]
+        L.mm_cov_workspace_size.argtypes = [i32, i32, i32, i32, i32, ctypes.POINTER(sz)]
+        L.mm_cov.argtypes = [i32, i32, P, i64, P, i32, i32, i32, P, P, P, sz, P]
+        L.mm_status_string.argtypes = [i32]
+        L.mm_status_string.restype = ctypes.c_char_p
+        L.mm_profile_enable.argtypes = [i32]
+        L.mm_profile_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(f64), ctypes.POINTER(i64)]
+        for name in EXPORTED:
+            if name != "mm_status_string":
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _status_text(s: int) -> str:
+    try:
+        return lib().mm_status_string(int(s)).decode()
+    except Exception:
+        return "status %d" % s
+
+
+def _check(status: int, where: str):
+    if status != MM_OK:
+        raise MMError(status, where)
+
+
+def _enum(value, table, what):
+    if isinstance(value, str):
+        key = value.lower()
+        if key not in table:
+            raise ValueError("unknown %s %r" % (what, value))
+        return table[key]
+    return int(value)
+
+
+def _tuning(tune):
+    if tune is None:
+        return None
+    if isinstance(tune, Tuning):
+        return tune
+    t = Tuning()
+    for k, v in dict(tune).items():
+        setattr(t, k, v)
+    return t
+
+
+def _ptr(x):
+    return ctypes.c_void_p(x.data_ptr()) if x is not None else None
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def plan_query(N: int, kernel="es", tol: float = 1e-12, prec="fp64", tune=None) -> dict:
+    info = PlanInfo()
+    t = _tuning(tune)
+    st = lib().mm_plan_query(int(N), _enum(kernel, _KERNELS, "kernel"), float(tol), _enum(prec, _PRECS, "precision"),
+                             ctypes.byref(t) if t is not None else None, ctypes.byref(info))
+    _check(st, "mm_plan_query")
+    return {f: getattr(info, f) for f, _ in PlanInfo._fields_}
+
+
+def nufft1_workspace_size(S: int, N: int, kernel="es", tol=1e-12, prec="fp64", tune=None) -> int:
+    out = ctypes.c_size_t(0)
+    t = _tuning(tune)
+    st = lib().mm_nufft1_workspace_size(int(S), int(N), _enum(kernel, _KERNELS, "kernel"), float(tol),
+                                        _enum(prec, _PRECS, "precision"), ctypes.byref(t) if t is not None else None,
+                                        ctypes.byref(out))
+    _check(st, "mm_nufft1_workspace_size")
+    return int(out.value)
+
+
+def _workspace(nbytes: int, device):
+    if nbytes == 0:
+        return None
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def nufft1(offsets: torch.Tensor, t: torch.Tensor, dp: torch.Tensor, t0: float, T: float, N: int, kernel="es",
+           tol: float = 1e-12, prec="fp64", tune=None, validate: bool = False, out: torch.Tensor = None,
+           ws: torch.Tensor = None) -> torch.Tensor:
+    """Coefficients c_k, k = 0..N, of every CSR series: (S, N+1) complex128
+    (prec "fp64") or complex64 (prec "mixed")."""
+    p = _enum(prec, _PRECS, "precision")
+    if not (offsets.is_cuda and t.is_cuda and dp.is_cuda):
+        raise ValueError("offsets, t and dp must be device tensors")
+    if offsets.dtype != torch.int64 or t.dtype != torch.float64 or dp.dtype not in (torch.float32, torch.float64):
+        raise TypeError("offsets int64, t float64, dp float32/float64 expected")
+    offsets, t, dp = offsets.contiguous(), t.contiguous(), dp.contiguous()
+    S = offsets.numel() - 1
+    cdt = torch.complex64 if p == MIXED else torch.complex128
+    if out is None:
+        out = torch.empty((S, N + 1), dtype=cdt, device=t.device)
+    if out.dtype != cdt or out.dim() != 2 or out.shape[0] != S or out.stride(1) != 1:
+        raise ValueError("out must be (S, ldc>=N+1) %s with unit column stride" % cdt)
+    need = nufft1_workspace_size(S, N, kernel, tol, prec, tune)
+    if ws is None or ws.numel() < need:
+        ws = _workspace(need, t.device)
+    tt = _tuning(tune)
+    st = lib().mm_nufft1(S, _ptr(offsets), _ptr(t), _ptr(dp), int(dp.dtype == torch.float64), float(t0), float(T),
+                         int(N), _enum(kernel, _KERNELS, "kernel"), float(tol), p,
+                         ctypes.byref(tt) if tt is not None else None, _ptr(out), out.stride(0), _ptr(ws),
+                         ws.numel() if ws is not None else 0, int(bool(validate)), _stream())
+    _check(st, "mm_nufft1")
+    return out
+
+
+def cov_workspace_size(G: int, D: int, Nmax: int, nN: int, prec="fp64") -> int:
+    out = ctypes.c_size_t(0)
+    _check(lib().mm_cov_workspace_size(int(G), int(D), int(Nmax), int(nN), _enum(prec, _PRECS, "precision"),
+                                       ctypes.byref(out)), "mm_cov_workspace_size")
+    return int(out.value)
+
+
+def cov(coef: torch.Tensor, G: int, D: int, Ns, basis="dirichlet", correlation: bool = True, ws: torch.Tensor = None):
+    """Sigma (and R) of shape (len(Ns), G, D, D) from (G*D, >=max(Ns)+1) coefficients."""
+    if coef.dtype == torch.complex64:
+        p, rdt = MIXED, torch.float32
+    elif coef.dtype == torch.complex128:
+        p, rdt = PLAIN_FP64, torch.float64
+    else:
+        raise TypeError("coef must be complex64 (mixed) or complex128 (fp64)")
+    if not coef.is_cuda or coef.dim() != 2 or coef.stride(1) != 1 or coef.shape[0] != G * D:
+        raise ValueError("coef must be a (G*D, ldc) device tensor with unit column stride")
+    Ns = [int(n) for n in Ns]
+    arr = (ctypes.c_int32 * len(Ns))(*Ns)
+    covt = torch.empty((len(Ns), G, D, D), dtype=rdt, device=coef.device)
+    corrt = torch.empty_like(covt) if correlation else None
+    need = cov_workspace_size(G, D, max(Ns), len(Ns), "mixed" if p == MIXED else "fp64")
+    if ws is None or ws.numel() < need:
+        ws = _workspace(need, coef.device)
+    st = lib().mm_cov(int(G), int(D), _ptr(coef), coef.stride(0), arr, len(Ns), _enum(basis, _BASES, "basis"), p,
+                      _ptr(covt), _ptr(corrt), _ptr(ws), ws.numel() if ws is not None else 0, _stream())
+    _check(st, "mm_cov")
+    return covt, corrt
+
+
+def estimate(w, Ns=None, basis="dirichlet", kernel="es", tol: float = 1e-12, prec="fp64", tune=None):
+    """Both stages for a ``synth.Workload`` already on the device."""
+    Ns = list(w.Ns if Ns is None else Ns)
+    coef = nufft1(w.offsets, w.t, w.dp, w.t0, w.T, max(Ns), kernel, tol, prec, tune)
+    S, R = cov(coef, w.G, w.D, Ns, basis)
+    return coef, S, R
+
+
+def profile_enable(on: bool = True):
+    _check(lib().mm_profile_enable(int(bool(on))), "mm_profile_enable")
+
+
+def profile_reset():
+    _check(lib().mm_profile_reset(), "mm_profile_reset")
+
+
+def profile_read(name=None):
+    ms = ctypes.c_double(0)
+    n = ctypes.c_int64(0)
+    _check(lib().mm_profile_read(name.encode() if name else None, ctypes.byref(ms), ctypes.byref(n)),
+           "mm_profile_read")
+    return float(ms.value), int(n.value)

@@ -113,7 +113,7 @@ def poisson_times(rate: float, T: float, gen, device="cpu"):
     out = []
     base = 0.0
     while True:
-        e = torch.empty(chunk, dtype=torch.float64, device=device).exponential_(1.0 / rate, generator=gen)
+        e = torch.empty(chunk, dtype=torch.float64, device=device).exponential_(rate, generator=gen)
         c = base + torch.cumsum(e, 0)
         keep = c[c < T]
         out.append(keep)

@@ -1,0 +1,122 @@
+"""Host-side checks of the C ABI: the library loads without a GPU, exports every
+entry point declared in include/mm.h, rejects invalid arguments before any device
+work, and plans grids and widths per the paper's rules."""
+import ctypes
+import json
+import os
+import re
+
+import pytest
+import torch  # noqa: F401  (load torch's HIP runtime first)
+
+from paper_2003_02842_amd import mm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GOLDEN = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_values.json")))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "mm.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mm_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = mm.lib()
+    syms = declared_symbols()
+    assert len(syms) >= 9
+    for s in syms:
+        assert hasattr(L, s), s
+    assert set(syms) == set(mm.EXPORTED)
+
+
+def test_status_strings():
+    for s in range(7):
+        assert mm.lib().mm_status_string(s)
+
+
+def _nufft_raw(**kw):
+    a = dict(S=2, offsets=1, t=1, dp=1, dpf=0, t0=0.0, T=1.0, N=10, kernel=2, tol=1e-6, prec=1, tune=None, coef=1,
+             ldc=11, ws=256, wsb=1 << 40, validate=0, stream=None)
+    a.update(kw)
+    P = ctypes.c_void_p
+    return mm.lib().mm_nufft1(a["S"], P(a["offsets"]), P(a["t"]), P(a["dp"]), a["dpf"], a["t0"], a["T"], a["N"],
+                              a["kernel"], a["tol"], a["prec"], a["tune"], P(a["coef"]), a["ldc"], P(a["ws"]),
+                              a["wsb"], a["validate"], a["stream"])
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(S=-1), mm.MM_ERR_ARG), (dict(N=0), mm.MM_ERR_ARG), (dict(T=0.0), mm.MM_ERR_ARG),
+    (dict(T=float("nan")), mm.MM_ERR_ARG), (dict(ldc=10), mm.MM_ERR_ARG), (dict(offsets=0), mm.MM_ERR_ARG),
+    (dict(coef=0), mm.MM_ERR_ARG), (dict(dpf=2), mm.MM_ERR_ARG), (dict(kernel=7), mm.MM_ERR_ARG),
+    (dict(prec=3), mm.MM_ERR_ARG), (dict(tol=1e-7), mm.MM_ERR_TOL), (dict(tol=0.5), mm.MM_ERR_TOL),
+    (dict(prec=0, tol=1e-15), mm.MM_ERR_TOL), (dict(tol=float("nan")), mm.MM_ERR_TOL),
+    (dict(wsb=16), mm.MM_ERR_WORKSPACE), (dict(ws=0), mm.MM_ERR_WORKSPACE), (dict(ws=257), mm.MM_ERR_ARG),
+    (dict(S=0), mm.MM_OK),
+])
+def test_nufft1_rejects_before_launch(kw, status):
+    assert _nufft_raw(**kw) == status
+
+
+def _cov_raw(**kw):
+    a = dict(G=1, D=3, coef=1, ldc=11, Ns=[5], basis=0, prec=1, cov=1, corr=0, ws=0, wsb=0)
+    a.update(kw)
+    P = ctypes.c_void_p
+    arr = (ctypes.c_int32 * max(1, len(a["Ns"])))(*a["Ns"]) if a["Ns"] is not None else None
+    n = a.get("nN", len(a["Ns"]) if a["Ns"] is not None else 1)
+    return mm.lib().mm_cov(a["G"], a["D"], P(a["coef"]), a["ldc"], arr, n, a["basis"], a["prec"], P(a["cov"]),
+                           P(a["corr"]), P(a["ws"]), a["wsb"], None)
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(G=0), mm.MM_ERR_ARG), (dict(D=0), mm.MM_ERR_ARG), (dict(coef=0), mm.MM_ERR_ARG),
+    (dict(cov=0), mm.MM_ERR_ARG), (dict(Ns=[11]), mm.MM_ERR_ARG), (dict(Ns=[0]), mm.MM_ERR_ARG),
+    (dict(Ns=None), mm.MM_ERR_ARG), (dict(nN=0), mm.MM_ERR_ARG), (dict(nN=129, Ns=[1] * 129), mm.MM_ERR_ARG),
+    (dict(basis=2), mm.MM_ERR_ARG), (dict(prec=9), mm.MM_ERR_ARG),
+    (dict(D=200, ldc=5001, Ns=[5000]), mm.MM_ERR_WORKSPACE),
+])
+def test_cov_rejects_before_launch(kw, status):
+    assert _cov_raw(**kw) == status
+
+
+def test_min_halfwidths_printed_in_paper():
+    g = GOLDEN["min_spread_halfwidth"]
+    for key, kern in (("gaussian", "g"), ("kaiser_bessel", "kb"), ("es", "es")):
+        info = mm.plan_query(100, kern, g[key]["tol"], "fp64")
+        assert info["msp"] == g[key]["msp"], key
+
+
+def test_grid_length_rule():
+    """M_r = sigma (2N+1) (Sec. 2.2.5); ours is the smallest even 2,3,5-smooth
+    length not below it, so it equals the printed value when that is smooth."""
+    for c in GOLDEN["grid_length_examples"]["cases"]:
+        Mr = mm.plan_query(c["N"], "es", 1e-6, "fp64")["Mr"]
+        assert Mr >= c["Mr"]
+        n, smooth = c["Mr"], True
+        for p in (2, 3, 5):
+            while n % p == 0:
+                n //= p
+        smooth = (n == 1)
+        if smooth:
+            assert Mr == c["Mr"]
+        assert Mr % 2 == 0
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 7, 100, 5000, 50000, 123457])
+@pytest.mark.parametrize("kern,tol,prec", [("es", 1e-12, "fp64"), ("g", 1e-6, "mixed"), ("kb", 1e-9, "fp64"),
+                                           ("es", 1e-1, "mixed")])
+def test_plan_invariants(N, kern, tol, prec):
+    p = mm.plan_query(N, kern, tol, prec)
+    assert p["Mr"] >= 2 * (2 * N + 1) and p["Mr"] >= 2 * p["width"] and p["Mr"] % 2 == 0
+    assert p["L1"] * p["L2"] * 2 == p["Mr"] and p["L1"] <= p["L2"] <= 2048
+    for n in (p["L1"], p["L2"]):
+        for q in (2, 3, 5):
+            while n % q == 0:
+                n //= q
+        assert n == 1
+
+
+def test_width_grows_as_tolerance_tightens():
+    for kern in ("g", "kb", "es"):
+        ws = [mm.plan_query(1000, kern, tol, "fp64")["width"] for tol in (1e-1, 1e-3, 1e-6, 1e-9, 1e-12, 1e-14)]
+        assert ws == sorted(ws) and ws[0] < ws[-1]

@@ -1,0 +1,170 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle.
+
+Bars: FP64 path within 1e-11 relative Frobenius of the oracle for Sigma and R
+(and per-series coefficient l2 error within the requested tolerance); mixed
+path (FP32 spreading/FFT, split-BF16 MFMA contraction) within 1e-5.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2003_02842_amd import synth
+from tests.helpers import need_gpu, relfro, series_rel_l2
+
+pytestmark = pytest.mark.gpu
+
+FP64_BAR = 1e-11
+MIXED_BAR = 1e-5
+
+
+@pytest.fixture(scope="module")
+def mm():
+    need_gpu()
+    from paper_2003_02842_amd import mm as m
+    return m
+
+
+def oracle_coef(w, N):
+    return oracle.coeffs_batch(w.offsets, w.t, w.dp, w.t0, w.T, N)
+
+
+def gpu_coef(mm, w, N, kernel, tol, prec, tune=None):
+    wd = w.to("cuda")
+    c = mm.nufft1(wd.offsets, wd.t, wd.dp, w.t0, w.T, N, kernel, tol, prec, tune)
+    torch.cuda.synchronize()
+    return c
+
+
+# ------------------------------------------------------------------ single jump
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed", 1e-6)])
+@pytest.mark.parametrize("kernel", ["es", "kb", "g"])
+@pytest.mark.parametrize("u", [0.0, 0.25, 0.5 - 2 ** -30, 1.0 - 2 ** -40, 1.0, 37.0 / 1350.0])
+def test_single_jump(mm, prec, tol, kernel, u):
+    N = 333
+    w = synth.single_jump(u, 0.7, dp_dtype=torch.float64 if prec == "fp64" else torch.float32)
+    c = gpu_coef(mm, w, N, kernel, tol, prec).cpu().numpy()
+    ref = oracle_coef(w, N)
+    err = series_rel_l2(c, ref)[0]
+    assert err <= tol * 2 + (2e-7 if prec == "mixed" else 1e-14), err
+
+
+# ------------------------------------------- tiny synchronous bivariate, FP64 path
+@pytest.mark.parametrize("kernel", ["es", "kb", "g"])
+def test_bivariate_sync_fp64(mm, kernel):
+    w = synth.bivariate_sync(n=10_000)
+    N = w.Ns[0]
+    c = gpu_coef(mm, w, N, kernel, 1e-12, "fp64")
+    ref = oracle_coef(w, N)
+    assert series_rel_l2(c, ref).max() <= 1e-12 * 5
+    for basis, b in (("dirichlet", oracle.DIRICHLET), ("fejer", oracle.FEJER)):
+        S, R = mm.cov(c, 1, 2, [N], basis)
+        So, Ro = oracle.cov(ref, 1, 2, [N], b)
+        assert relfro(S.cpu().numpy(), So) <= FP64_BAR
+        assert relfro(R.cpu().numpy(), Ro) <= FP64_BAR
+
+
+# --------------------------------------------- asynchronous bivariate, N sweep, mixed
+@pytest.mark.parametrize("kernel", ["es", "kb", "g"])
+@pytest.mark.parametrize("basis", ["dirichlet", "fejer"])
+def test_bivariate_async_sweep_mixed(mm, kernel, basis):
+    w = synth.bivariate_async()
+    assert len(w.Ns) >= 30
+    Nmax = max(w.Ns)
+    c = gpu_coef(mm, w, Nmax, kernel, 1e-6, "mixed")
+    S, R = mm.cov(c, 1, 2, w.Ns, basis)
+    ref = oracle_coef(w, Nmax)
+    So, Ro = oracle.cov(ref, 1, 2, w.Ns, oracle.DIRICHLET if basis == "dirichlet" else oracle.FEJER)
+    S, R = S.cpu().numpy(), R.cpu().numpy()
+    for q in range(len(w.Ns)):
+        assert relfro(S[q], So[q]) <= MIXED_BAR, (w.Ns[q], relfro(S[q], So[q]))
+        assert relfro(R[q], Ro[q]) <= MIXED_BAR, (w.Ns[q], relfro(R[q], Ro[q]))
+
+
+# ------------------------------------------ ragged series, empty series, many tiles
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed", 1e-6)])
+@pytest.mark.parametrize("tile", [64, 200, 0])
+@pytest.mark.parametrize("kernel", ["es", "g", "kb"])
+def test_ragged_many_tiles(mm, prec, tol, tile, kernel):
+    w = synth.random_events(9, 0, 700, seed=123, dp_dtype=torch.float64 if prec == "fp64" else torch.float32)
+    counts = (w.offsets[1:] - w.offsets[:-1]).tolist()
+    N = 333
+    tune = {"tile": tile} if tile else None
+    c = gpu_coef(mm, w, N, kernel, tol, prec, tune)
+    ref = oracle_coef(w, N)
+    err = series_rel_l2(c, ref)
+    bar = tol * 2 + (2e-7 if prec == "mixed" else 1e-14)
+    for s, n in enumerate(counts):
+        if n == 0:
+            assert np.all(c[s].cpu().numpy() == 0)
+        else:
+            assert err[s] <= bar, (s, n, err[s])
+    S, R = mm.cov(c, 1, 9, [N, 17], "fejer")
+    So, Ro = oracle.cov(ref, 1, 9, [N, 17], oracle.FEJER)
+    bar2 = FP64_BAR if prec == "fp64" else MIXED_BAR
+    assert relfro(S.cpu().numpy(), So) <= bar2
+    assert relfro(R.cpu().numpy(), Ro) <= bar2
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed", 1e-6)])
+def test_edge_times(mm, prec, tol):
+    """Events exactly at t0, exactly at T (the same point as t0), on grid nodes,
+    and duplicated timestamps."""
+    N = 40
+    Mr = mm.plan_query(N, "es", tol, prec)["Mr"]
+    T = 3.0
+    t = torch.tensor([0.0, 0.0, T * 5 / Mr, T * 0.5, T * (Mr - 1) / Mr, T], dtype=torch.float64)
+    dp = torch.tensor([0.1, -0.2, 0.3, 0.05, -0.4, 0.25], dtype=torch.float64 if prec == "fp64" else torch.float32)
+    w = synth.Workload("edge", torch.tensor([0, 6], dtype=torch.int64), t, dp, 0.0, T, 1, 1, [N], 0, {})
+    c = gpu_coef(mm, w, N, "es", tol, prec)
+    ref = oracle_coef(w, N)
+    assert series_rel_l2(c, ref)[0] <= tol * 2 + (2e-7 if prec == "mixed" else 1e-14)
+
+
+def test_validate_rejects_bad_data(mm):
+    base = synth.random_events(3, 5, 20, seed=4)
+    good = base.to("cuda")
+    mm.nufft1(good.offsets, good.t, good.dp, 0.0, 1.0, 10, "es", 1e-6, "fp64", validate=True)
+    bad_cases = []
+    t = good.t.clone(); t[3], t[4] = t[4].item(), t[3].item() + 1e-9; bad_cases.append((t, good.dp))
+    t = good.t.clone(); t[0] = 1.5; bad_cases.append((t, good.dp))
+    d = good.dp.clone(); d[2] = float("nan"); bad_cases.append((good.t, d))
+    t = good.t.clone(); t[1] = float("inf"); bad_cases.append((t, good.dp))
+    for tt, dd in bad_cases:
+        with pytest.raises(mm.MMError) as ei:
+            mm.nufft1(good.offsets, tt, dd, 0.0, 1.0, 10, "es", 1e-6, "fp64", validate=True)
+        assert ei.value.status == mm.MM_ERR_DATA
+
+
+# ------------------------------------------- cross-section (MFMA contraction), reduced horizon
+def test_cross_section_mfma(mm):
+    w = synth.cross_section(D=100, T_sec=7200.0, N=5000, seed=99)
+    N = 5000
+    c = gpu_coef(mm, w, N, "es", 1e-6, "mixed")
+    S, R = mm.cov(c, 1, 100, [N], "fejer")
+    ref = oracle_coef(w, N)
+    So, Ro = oracle.cov(ref, 1, 100, [N], oracle.FEJER)
+    eS, eR = relfro(S.cpu().numpy(), So), relfro(R.cpu().numpy(), Ro)
+    assert eS <= MIXED_BAR and eR <= MIXED_BAR, (eS, eR)
+    # the same coefficients through the FP64 contraction
+    c64 = gpu_coef(mm, w, N, "es", 1e-12, "fp64")
+    S64, R64 = mm.cov(c64, 1, 100, [N], "fejer")
+    assert relfro(S64.cpu().numpy(), So) <= FP64_BAR
+
+
+# ----------------------------------------------- Monte Carlo replicates, reduced G
+@pytest.mark.parametrize("basis", ["dirichlet", "fejer"])
+def test_epps_replicates_sweep(mm, basis):
+    w = synth.epps_replicates(G=12, seed=31)
+    Nmax = max(w.Ns)
+    c = gpu_coef(mm, w, Nmax, "es", 1e-6, "mixed")
+    S, R = mm.cov(c, w.G, w.D, w.Ns, basis)
+    ref = oracle_coef(w, Nmax)
+    So, Ro = oracle.cov(ref, w.G, w.D, w.Ns, oracle.DIRICHLET if basis == "dirichlet" else oracle.FEJER)
+    S, R = S.cpu().numpy(), R.cpu().numpy()
+    for q in range(len(w.Ns)):
+        for g in range(w.G):
+            assert relfro(S[q, g], So[q, g]) <= MIXED_BAR
+            assert relfro(R[q, g], Ro[q, g]) <= MIXED_BAR
