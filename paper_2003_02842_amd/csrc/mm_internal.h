@@ -60,7 +60,7 @@ struct Plan {
     FFTDesc F1, F2;
     int CB;              // columns per block of the column pass
     int R;               // row pairs per block of the row pass
-    int tile;            // cells per spreading tile
+    int tile;            // cells per spreading tile: 1024, 2048 or 4096 (256 threads x 4, 8, 16 cells)
     int fused;           // 1: single-workgroup LDS-resident NUFFT per series
     int fused_threads;
 };
@@ -73,7 +73,7 @@ void gauss_legendre_pos(int n_pos, double* x, double* w);   // nodes/weights on 
 
 // Workspace layout of one mm_nufft1 call.
 struct NufftWs {
-    size_t tw1, tw2, twL, twM, rev1, pos2, dfac, flag, grid, total;
+    size_t tw1, tw2, twL, twM, rev1, pos2, dfac, flag, ranges, grid, total;
     int S_grid;   // series whose grids are resident at once
 };
 NufftWs nufft_workspace(const Plan& p, int32_t S);

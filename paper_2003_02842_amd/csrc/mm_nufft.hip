@@ -1,8 +1,11 @@
 // gfx950 kernels of the type-1 NUFFT (Sec. 2.2.5 of the paper):
 //   k_prep      FP64 tables: FFT twiddles, digit-reversal maps, deconvolution
 //               factors 1/(2 pi psi_hat(k/Mr)) of the averaging kernel
+//   k_tile_ranges  per (series, grid tile) event ranges by binary search on the
+//               sorted event keys
 //   k_spread    spreading onto the periodic oversampled grid (Eq. Der:15), one
-//               workgroup per (series, grid tile), LDS accumulation, no global atomics
+//               workgroup per (series, grid tile), each cell gathering its events
+//               from LDS; no atomics
 //   k_fft_cols  first pass of the grid FFT (Eq. Der:16): length-L1 transforms of
 //               strided columns of the L1 x L2 view of the packed complex grid,
 //               times the four-step twiddle, in place
@@ -142,140 +145,179 @@ __device__ __forceinline__ void cell_of(double t, double t0, double span, double
 __device__ __forceinline__ float fexp2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
-// Add the w taps of one event (strength v, fraction f) to acc[base + j], j < w,
-// keeping only cells inside [0, len).
+// Kernel constants in the working precision, prepared once per thread.
+template <typename T>
+struct KEval {
+    T inv_hw, es_c;        // ES: exp(beta (sqrt(1 - (x/hw)^2) - 1)); es_c = beta (log2 e for FP32)
+    T g_c;                 // Gaussian: exp(-t1 x^2); g_c = t1 (times log2 e for FP32)
+    T kb_m2, kb_b, kb_inv_norm;
+    __device__ explicit KEval(const KernParams& kp)
+    {
+        const double l2e = (sizeof(T) == 4) ? 1.4426950408889634074 : 1.0;
+        inv_hw = (T)kp.es_inv_hw;
+        es_c = (T)(kp.es_beta * l2e);
+        g_c = (T)(kp.g_t1 * l2e);
+        kb_m2 = (T)(kp.kb_m * kp.kb_m);
+        kb_b = (T)kp.kb_b;
+        kb_inv_norm = (T)kp.kb_inv_norm;
+    }
+};
+
+// The averaging kernel at cell distance x (|x| <= w/2), normalised to 1 at 0:
+//   ES  exp(beta (sqrt(1 - (x/hw)^2) - 1))          (Eq. Der:10, support w cells)
+//   G   exp(-t1 x^2), t1 = pi / lambda               (Eq. Der:5 in cells)
+//   KB  inv_norm sinh(b s)/s, s = sqrt(m^2 - x^2),   (Eq. Der:8 in cells; sin(b s')/s'
+//       s' = sqrt(x^2 - m^2) beyond |x| = m)
 template <typename T, int KIND>
-__device__ __forceinline__ void spread_event(T* acc, int len, int base, double f, T v, const KernParams& kp)
+__device__ __forceinline__ T kern_eval(T x, const KEval<T>& k)
 {
-    const int w = kp.w;
     if (KIND == MM_ES) {
-        // phi(x) = exp(beta (sqrt(1 - (x/hw)^2) - 1)), |x| <= hw (Eq. Der:10 rescaled to w cells)
-        const T x0 = (T)(1.0 - f - kp.hw);
-        const T inv = (T)kp.es_inv_hw;
-        if constexpr (sizeof(T) == 4) {
-            const float b2 = (float)(kp.es_beta * 1.4426950408889634074);
-            for (int j = 0; j < w; ++j) {
-                int pos = base + j;
-                if ((unsigned)pos < (unsigned)len) {
-                    float z = (x0 + (float)j) * inv;
-                    float s = fsqrt(fmaxf(1.0f - z * z, 0.0f));
-                    atomicAdd(&acc[pos], v * fexp2(b2 * (s - 1.0f)));
-                }
-            }
-        } else {
-            const double beta = kp.es_beta;
-            for (int j = 0; j < w; ++j) {
-                int pos = base + j;
-                if ((unsigned)pos < (unsigned)len) {
-                    double z = (x0 + (double)j) * inv;
-                    double s = sqrt(fmax(1.0 - z * z, 0.0));
-                    atomicAdd(&acc[pos], v * exp(beta * (s - 1.0)));
-                }
-            }
-        }
+        T z = x * k.inv_hw;
+        if constexpr (sizeof(T) == 4) return fexp2(k.es_c * (fsqrt(fmaxf(1.0f - z * z, 0.0f)) - 1.0f));
+        else return exp(k.es_c * (sqrt(fmax(1.0 - z * z, 0.0)) - 1.0));
     } else if (KIND == MM_GAUSSIAN) {
-        // Fast Gaussian gridding (Eq. Der:20): phi(k - f) = E1 E2^k E3_k with
-        // E1 = exp(-t1 f^2), E2 = exp(2 t1 f), E3_k = exp(-t1 k^2); taps k = -(msp-1)..msp.
-        const int msp = kp.g_msp;
-        const T t1 = (T)kp.g_t1;
-        const T ff = (T)f;
-        const T E1 = exp(-t1 * ff * ff);
-        const T E2 = exp((T)2 * t1 * ff);
-        const int jc = base + msp - 1;            // cell of k = 0
-        if ((unsigned)jc < (unsigned)len) atomicAdd(&acc[jc], v * E1);
-        T p = E1;
-        for (int k = 1; k <= msp; ++k) {
-            p *= E2;
-            int pos = jc + k;
-            if ((unsigned)pos < (unsigned)len) atomicAdd(&acc[pos], v * (p * (T)kp.g_e3[k]));
-        }
-        const T iE2 = (T)1 / E2;
-        p = E1;
-        for (int k = 1; k < msp; ++k) {
-            p *= iE2;
-            int pos = jc - k;
-            if ((unsigned)pos < (unsigned)len) atomicAdd(&acc[pos], v * (p * (T)kp.g_e3[k]));
-        }
+        if constexpr (sizeof(T) == 4) return fexp2(-k.g_c * x * x);
+        else return exp(-k.g_c * x * x);
     } else {
-        // Kaiser-Bessel (Eq. Der:8 in cells): inv_norm sinh(b s)/s, s = sqrt(m^2 - x^2),
-        // continued by sin(b s')/s', s' = sqrt(x^2 - m^2), outside |x| <= m.
-        const T x0 = (T)(1.0 - f - kp.hw);
-        const T m2 = (T)(kp.kb_m * kp.kb_m), b = (T)kp.kb_b, inv_norm = (T)kp.kb_inv_norm;
-        for (int j = 0; j < w; ++j) {
-            int pos = base + j;
-            if ((unsigned)pos >= (unsigned)len) continue;
-            T x = x0 + (T)j;
-            T s2 = m2 - x * x;
-            T val;
-            if (s2 > (T)0) {
-                T s = sqrt(s2);
-                T a = b * s;
-                if constexpr (sizeof(T) == 4) {
-                    if (a < 0.5f) {
-                        float a2 = a * a;
-                        val = b * (1.0f + a2 * (1.0f / 6 + a2 * (1.0f / 120 + a2 * (1.0f / 5040))));
-                    } else {
-                        float E = expf(a);
-                        val = (E - 1.0f / E) / (2.0f * s);
-                    }
+        T s2 = k.kb_m2 - x * x;
+        T val;
+        if (s2 > (T)0) {
+            T s = sqrt(s2);
+            T a = k.kb_b * s;
+            if constexpr (sizeof(T) == 4) {
+                if (a < 0.5f) {
+                    float a2 = a * a;
+                    val = k.kb_b * (1.0f + a2 * (1.0f / 6 + a2 * (1.0f / 120 + a2 * (1.0f / 5040))));
                 } else {
-                    val = sinh(a) / s;
+                    float E = expf(a);
+                    val = (E - 1.0f / E) / (2.0f * s);
                 }
-            } else if (s2 < (T)0) {
-                T s = sqrt(-s2);
-                val = sin(b * s) / s;
             } else {
-                val = b;
+                val = sinh(a) / s;
             }
-            atomicAdd(&acc[pos], v * (val * inv_norm));
+        } else if (s2 < (T)0) {
+            T s = sqrt(-s2);
+            val = sin(k.kb_b * s) / s;
+        } else {
+            val = k.kb_b;
         }
+        return val * k.kb_inv_norm;
     }
 }
 
-template <typename T, typename DPT, int KIND, bool EXACT_DIV>
-__global__ __launch_bounds__(256) void k_spread(const int64_t* __restrict__ offsets, const double* __restrict__ t,
-                                                const DPT* __restrict__ dp, int s_begin, double t0, double span,
-                                                double inv_span, KernParams kp, int Mr, int tile,
+// Event ranges of every (series, tile): for m = -1, 0, 1 the events whose taps
+// [l0, l0 + w) meet cells [a, a + len) + m Mr, i.e. keys l0 in
+// [a + m Mr - w + 1, a + len + m Mr); entry 2(m+1) is the first such event and
+// 2(m+1)+1 one past the last (lower bounds on the sorted keys).
+template <bool EXACT_DIV>
+__global__ void k_tile_ranges(const int64_t* __restrict__ offsets, const double* __restrict__ t, int s_begin,
+                              int s_count, int tiles, int tc, int Mr, int w, double hw, double t0, double span,
+                              double inv_span, int64_t* __restrict__ ranges)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)s_count * tiles * 6) return;
+    const int q = (int)(idx % 6);
+    const int64_t rest = idx / 6;
+    const int tile = (int)(rest % tiles);
+    const int s = s_begin + (int)(rest / tiles);
+    const int64_t a = (int64_t)tile * tc;
+    const int64_t len = min((int64_t)tc, (int64_t)Mr - a);
+    const int64_t m = (int64_t)(q >> 1) - 1;
+    const int64_t key = (q & 1) ? a + len + m * Mr : a + m * Mr - w + 1;
+    int64_t lo = offsets[s], hi = offsets[s + 1];
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        int64_t l0;
+        double f;
+        cell_of<EXACT_DIV>(t[mid], t0, span, inv_span, Mr, hw, l0, f);
+        if (l0 < key) lo = mid + 1;
+        else hi = mid;
+    }
+    ranges[idx] = lo;
+}
+
+template <typename T>
+struct EvRec {
+    int key;   // first-tap cell relative to the tile, plus w - 1 (>= 0)
+    T x0;      // kernel argument of the first tap, 1 - f - hw
+    T v;       // event strength
+};
+
+// Spreading (Eq. Der:15) by gathering: one workgroup per (series, tile of
+// 256*CPT cells); thread tid owns cells tid + 256 r.  The tile's events, sorted
+// by key, are staged in LDS in chunks together with first[k] = number of staged
+// events with key < k; cell c then sums over the contiguous events with keys in
+// [c, c + w - 1].  No atomics: each grid value is one thread's register sum.
+template <typename T, typename DPT, int KIND, int CPT>
+__global__ __launch_bounds__(256) void k_spread(const double* __restrict__ t, const DPT* __restrict__ dp,
+                                                double t0, double span, double inv_span, KernParams kp, int Mr,
+                                                const int64_t* __restrict__ ranges, int tiles,
                                                 T* __restrict__ grid, int64_t grid_stride)
 {
-    extern __shared__ __align__(16) char smem_raw[];
-    T* acc = reinterpret_cast<T*>(smem_raw);
-    __shared__ int64_t rng[6];
-    const int s = s_begin + blockIdx.y;
-    const int a = blockIdx.x * tile;
-    const int len = min(tile, Mr - a);
-    for (int i = threadIdx.x; i < len; i += blockDim.x) acc[i] = (T)0;
-    const int64_t e0 = offsets[s], e1 = offsets[s + 1];
-    if (threadIdx.x < 6) {
-        // Events whose taps [l0, l0 + w) meet cells [a, a + len) + m Mr, m = -1, 0, 1:
-        // keys in [a + m Mr - w + 1, a + len + m Mr).
-        const int64_t m = (int64_t)(threadIdx.x >> 1) - 1;
-        const int64_t key = (threadIdx.x & 1) ? (int64_t)a + len + m * Mr : (int64_t)a + m * Mr - kp.w + 1;
-        int64_t lo = e0, hi = e1;
-        while (lo < hi) {
-            int64_t mid = (lo + hi) >> 1;
-            int64_t l0;
-            double f;
-            cell_of<EXACT_DIV>(t[mid], t0, span, inv_span, Mr, kp.hw, l0, f);
-            if (l0 < key) lo = mid + 1;
-            else hi = mid;
-        }
-        rng[threadIdx.x] = lo;
-    }
-    __syncthreads();
+    constexpr bool EXACT_DIV = sizeof(T) == 8;
+    constexpr int TC = 256 * CPT;
+    constexpr int EC = sizeof(T) == 4 ? 2048 : 1024;
+    __shared__ EvRec<T> ev[EC];
+    __shared__ unsigned short first[TC + kMaxTaps + 2];
+    const int a = blockIdx.x * TC;
+    const int len = min(TC, Mr - a);
+    const int w = kp.w;
+    const KEval<T> ke(kp);
+    const int64_t* rg = ranges + ((int64_t)blockIdx.y * tiles + blockIdx.x) * 6;
+    T acc[CPT];
+#pragma unroll
+    for (int r = 0; r < CPT; ++r) acc[r] = (T)0;
     for (int mi = 0; mi < 3; ++mi) {
-        const int64_t b0 = rng[2 * mi], b1 = rng[2 * mi + 1];
+        const int64_t b0 = rg[2 * mi], b1 = rg[2 * mi + 1];
         const int64_t shift = (int64_t)a + (int64_t)(mi - 1) * Mr;
-        for (int64_t i = b0 + threadIdx.x; i < b1; i += blockDim.x) {
-            int64_t l0;
-            double f;
-            cell_of<EXACT_DIV>(t[i], t0, span, inv_span, Mr, kp.hw, l0, f);
-            spread_event<T, KIND>(acc, len, (int)(l0 - shift), f, (T)dp[i], kp);
+        for (int64_t cb = b0; cb < b1; cb += EC) {
+            const int n = (int)min((int64_t)EC, b1 - cb);
+            __syncthreads();
+            for (int i = threadIdx.x; i < n; i += 256) {
+                int64_t l0;
+                double f;
+                cell_of<EXACT_DIV>(t[cb + i], t0, span, inv_span, Mr, kp.hw, l0, f);
+                EvRec<T> r;
+                r.key = (int)(l0 - shift) + w - 1;
+                r.x0 = (T)(1.0 - f - kp.hw);
+                r.v = (T)dp[cb + i];
+                ev[i] = r;
+            }
+            __syncthreads();
+            const int kmin = ev[0].key, kmax = ev[n - 1].key;
+            for (int i = 1 + threadIdx.x; i < n; i += 256) {
+                const int k1 = ev[i].key;
+                for (int k = ev[i - 1].key + 1; k <= k1; ++k) first[k] = (unsigned short)i;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < CPT; ++r) {
+                const int c = threadIdx.x + 256 * r;
+                if (c >= len || c + w - 1 < kmin || c > kmax) continue;
+                const int lo = (c <= kmin) ? 0 : first[c];
+                const int hi = (c + w > kmax) ? n : first[c + w];
+                const int cw = c + w - 1;
+                T s0 = (T)0, s1 = (T)0;
+                int e = lo;
+                for (; e + 1 < hi; e += 2) {
+                    const EvRec<T> p = ev[e], q = ev[e + 1];
+                    s0 += p.v * kern_eval<T, KIND>((T)(cw - p.key) + p.x0, ke);
+                    s1 += q.v * kern_eval<T, KIND>((T)(cw - q.key) + q.x0, ke);
+                }
+                if (e < hi) {
+                    const EvRec<T> p = ev[e];
+                    s0 += p.v * kern_eval<T, KIND>((T)(cw - p.key) + p.x0, ke);
+                }
+                acc[r] += s0 + s1;
+            }
         }
     }
-    __syncthreads();
     T* out = grid + (int64_t)blockIdx.y * grid_stride + a;
-    for (int i = threadIdx.x; i < len; i += blockDim.x) out[i] = acc[i];
+#pragma unroll
+    for (int r = 0; r < CPT; ++r) {
+        const int c = threadIdx.x + 256 * r;
+        if (c < len) out[c] = acc[r];
+    }
 }
 
 template <typename T>
@@ -514,31 +556,32 @@ hipError_t launch_validate(int32_t S, const int64_t* offsets, const double* t, c
 }
 
 template <typename T, typename DPT, int KIND>
-static void launch_spread_t(const Plan& p, int s_begin, int s_count, const int64_t* offsets, const double* t,
-                            const DPT* dp, double t0, double t_end, T* grid, int64_t grid_stride, hipStream_t st)
+static void launch_spread_t(const Plan& p, int s_count, const double* t, const DPT* dp, double t0, double t_end,
+                            const int64_t* ranges, int tiles, T* grid, int64_t grid_stride, hipStream_t st)
 {
-    const int tiles = (p.Mr + p.tile - 1) / p.tile;
-    const size_t lds = (size_t)p.tile * sizeof(T);
     const double span = t_end - t0;
-    if (p.prec == MM_PLAIN_FP64)
-        hipLaunchKernelGGL((k_spread<T, DPT, KIND, true>), dim3(tiles, s_count), dim3(256), lds, st, offsets, t, dp,
-                           s_begin, t0, span, 1.0 / span, p.kp, p.Mr, p.tile, grid, grid_stride);
+    const dim3 g(tiles, s_count);
+    if (p.tile <= 1024)
+        hipLaunchKernelGGL((k_spread<T, DPT, KIND, 4>), g, dim3(256), 0, st, t, dp, t0, span, 1.0 / span, p.kp, p.Mr,
+                           ranges, tiles, grid, grid_stride);
+    else if (p.tile <= 2048)
+        hipLaunchKernelGGL((k_spread<T, DPT, KIND, 8>), g, dim3(256), 0, st, t, dp, t0, span, 1.0 / span, p.kp, p.Mr,
+                           ranges, tiles, grid, grid_stride);
     else
-        hipLaunchKernelGGL((k_spread<T, DPT, KIND, false>), dim3(tiles, s_count), dim3(256), lds, st, offsets, t,
-                           dp, s_begin, t0, span, 1.0 / span, p.kp, p.Mr, p.tile, grid, grid_stride);
+        hipLaunchKernelGGL((k_spread<T, DPT, KIND, 16>), g, dim3(256), 0, st, t, dp, t0, span, 1.0 / span, p.kp,
+                           p.Mr, ranges, tiles, grid, grid_stride);
 }
 
 template <typename T, typename DPT>
-static void launch_spread_k(const Plan& p, int s_begin, int s_count, const int64_t* offsets, const double* t,
-                            const DPT* dp, double t0, double t_end, T* grid, int64_t grid_stride, hipStream_t st)
+static void launch_spread_k(const Plan& p, int s_count, const double* t, const DPT* dp, double t0, double t_end,
+                            const int64_t* ranges, int tiles, T* grid, int64_t grid_stride, hipStream_t st)
 {
     if (p.kernel == MM_ES)
-        launch_spread_t<T, DPT, MM_ES>(p, s_begin, s_count, offsets, t, dp, t0, t_end, grid, grid_stride, st);
+        launch_spread_t<T, DPT, MM_ES>(p, s_count, t, dp, t0, t_end, ranges, tiles, grid, grid_stride, st);
     else if (p.kernel == MM_GAUSSIAN)
-        launch_spread_t<T, DPT, MM_GAUSSIAN>(p, s_begin, s_count, offsets, t, dp, t0, t_end, grid, grid_stride, st);
+        launch_spread_t<T, DPT, MM_GAUSSIAN>(p, s_count, t, dp, t0, t_end, ranges, tiles, grid, grid_stride, st);
     else
-        launch_spread_t<T, DPT, MM_KAISER_BESSEL>(p, s_begin, s_count, offsets, t, dp, t0, t_end, grid, grid_stride,
-                                                  st);
+        launch_spread_t<T, DPT, MM_KAISER_BESSEL>(p, s_count, t, dp, t0, t_end, ranges, tiles, grid, grid_stride, st);
 }
 
 static int ilog2(int x)
@@ -556,11 +599,23 @@ static hipError_t nufft_tiled_t(const Plan& p, const NufftWs& w, char* ws, int32
     using C = typename CT<T>::type;
     T* grid = (T*)(ws + w.grid);
     const int64_t gstride = p.Mr;
+    const int tiles = (p.Mr + p.tile - 1) / p.tile;
+    int64_t* ranges = (int64_t*)(ws + w.ranges);
+    const double span = T_ - t0;
+    const int64_t nr = (int64_t)s_count * tiles * 6;
+    prof_begin("k_tile_ranges", st);
+    if (p.prec == MM_PLAIN_FP64)
+        hipLaunchKernelGGL(k_tile_ranges<true>, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, st, offsets, t,
+                           s_begin, s_count, tiles, p.tile, p.Mr, p.kp.w, p.kp.hw, t0, span, 1.0 / span, ranges);
+    else
+        hipLaunchKernelGGL(k_tile_ranges<false>, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, st, offsets, t,
+                           s_begin, s_count, tiles, p.tile, p.Mr, p.kp.w, p.kp.hw, t0, span, 1.0 / span, ranges);
+    prof_end("k_tile_ranges", st);
     prof_begin("k_spread", st);
     if (dp_fp64)
-        launch_spread_k<T, double>(p, s_begin, s_count, offsets, t, (const double*)dp, t0, T_, grid, gstride, st);
+        launch_spread_k<T, double>(p, s_count, t, (const double*)dp, t0, T_, ranges, tiles, grid, gstride, st);
     else
-        launch_spread_k<T, float>(p, s_begin, s_count, offsets, t, (const float*)dp, t0, T_, grid, gstride, st);
+        launch_spread_k<T, float>(p, s_count, t, (const float*)dp, t0, T_, ranges, tiles, grid, gstride, st);
     prof_end("k_spread", st);
 
     const int cbs = ilog2(p.CB);

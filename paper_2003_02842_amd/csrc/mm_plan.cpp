@@ -198,12 +198,8 @@ mm_status make_plan(int32_t N, mm_kernel kernel, double tol, mm_prec prec, const
     while (R > 1 && (size_t)(2 * R * (L2 | 1) + L2) * cs > budget) R >>= 1;
     while (R > 1 && R / 2 >= P) R >>= 1;         // stays a power of two
     p->R = R;
-    int tile = (prec == MM_MIXED) ? 16384 : 8192;
-    if (tune && tune->tile > 0) tile = tune->tile;
-    const int max_tile = (prec == MM_MIXED) ? 16384 : 8192;   // 64 KB of LDS
-    if (tile > max_tile) tile = max_tile;
-    if (tile > p->Mr) tile = p->Mr;
-    if (tile < 64) tile = std::min(64, p->Mr);
+    int tile = (prec == MM_MIXED) ? 2048 : 1024;
+    if (tune && tune->tile > 0) tile = tune->tile <= 1024 ? 1024 : (tune->tile <= 2048 ? 2048 : 4096);
     p->tile = tile;
     p->fused = 0;
     p->fused_threads = 256;
@@ -226,6 +222,8 @@ NufftWs nufft_workspace(const Plan& p, int32_t S)
     w.dfac = o; o += al(rs * (size_t)(p.N + 1));
     w.flag = o; o += 256;
     w.S_grid = (p.prec == MM_MIXED && !p.fused) ? S : (p.fused ? 0 : 1);
+    const size_t tiles = (size_t)(p.Mr + p.tile - 1) / p.tile;
+    w.ranges = o; o += al(8 * 6 * tiles * (size_t)w.S_grid);
     w.grid = o; o += al(rs * (size_t)p.Mr * (size_t)w.S_grid);
     w.total = o;
     return w;

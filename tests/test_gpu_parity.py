@@ -85,12 +85,17 @@ def test_bivariate_async_sweep_mixed(mm, kernel, basis):
 
 # ------------------------------------------ ragged series, empty series, many tiles
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed", 1e-6)])
-@pytest.mark.parametrize("tile", [64, 200, 0])
+@pytest.mark.parametrize("tile", [1024, 4096, 0])
 @pytest.mark.parametrize("kernel", ["es", "g", "kb"])
 def test_ragged_many_tiles(mm, prec, tol, tile, kernel):
-    w = synth.random_events(9, 0, 700, seed=123, dp_dtype=torch.float64 if prec == "fp64" else torch.float32)
+    """Uneven and empty series over a grid of several tiles (Mr = 12150); one
+    dense series (about 4 events per cell) makes tiles span several LDS chunks."""
+    w = synth.random_events(9, 0, 3000, seed=123, dp_dtype=torch.float64 if prec == "fp64" else torch.float32)
+    dense = synth.random_events(1, 50_000, 50_000, seed=7, dp_dtype=w.dp.dtype)
+    w = synth.Workload("ragged", torch.cat([w.offsets, w.offsets[-1] + dense.offsets[1:]]),
+                       torch.cat([w.t, dense.t]), torch.cat([w.dp, dense.dp]), 0.0, 1.0, 1, 10, [1], 0, {})
     counts = (w.offsets[1:] - w.offsets[:-1]).tolist()
-    N = 333
+    N = 3000
     tune = {"tile": tile} if tile else None
     c = gpu_coef(mm, w, N, kernel, tol, prec, tune)
     ref = oracle_coef(w, N)
@@ -101,8 +106,8 @@ def test_ragged_many_tiles(mm, prec, tol, tile, kernel):
             assert np.all(c[s].cpu().numpy() == 0)
         else:
             assert err[s] <= bar, (s, n, err[s])
-    S, R = mm.cov(c, 1, 9, [N, 17], "fejer")
-    So, Ro = oracle.cov(ref, 1, 9, [N, 17], oracle.FEJER)
+    S, R = mm.cov(c, 1, 10, [N, 17], "fejer")
+    So, Ro = oracle.cov(ref, 1, 10, [N, 17], oracle.FEJER)
     bar2 = FP64_BAR if prec == "fp64" else MIXED_BAR
     assert relfro(S.cpu().numpy(), So) <= bar2
     assert relfro(R.cpu().numpy(), Ro) <= bar2
