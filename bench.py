@@ -48,11 +48,27 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU-oracle sample time")
     ap.add_argument("--width", type=int, default=0, help="override the spreading width")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device-to-device copy (scales FETCH_SIZE/WRITE_SIZE counters)")
     return ap.parse_args()
+
+
+def copy_calibration():
+    import torch
+    n = 1 << 30
+    src = torch.ones(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "copies": 3}), flush=True)
+    return 0
 
 
 def main():
     a = parse()
+    if a.copy_calibration:
+        return copy_calibration()
     if a.gpus != 1:
         print("bench.py: this build runs on exactly one GPU; --gpus %d is not supported" % a.gpus, file=sys.stderr)
         return 2

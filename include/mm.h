@@ -65,7 +65,9 @@ typedef enum {
 /* Optional overrides of the planner (an autotuner's output).  Zero means "let
  * the planner choose"; pass NULL for all defaults. */
 typedef struct {
-    int32_t width;             /* taps per event (>= 2, <= 40) */
+    int32_t width;             /* taps per event (>= 2, <= 40); 0: MM_MIXED picks the smallest width whose
+                                  a-priori error estimate meets tol, MM_PLAIN_FP64 uses the paper's rule;
+                                  -1: the paper's rule for both */
     double sigma;              /* oversampling factor of the grid, >= 1.25 */
     int32_t tile;              /* cells per spreading tile (tiled path) */
     int32_t fused;             /* -1: never use the LDS-resident fused path, 0: auto, 1: prefer it */
@@ -84,12 +86,16 @@ typedef struct {
     double sigma;              /* oversampling factor used in the kernel shape rules */
     double beta;               /* ES beta, Gaussian lambda or Kaiser-Bessel b */
     double tol;
+    double est_err;            /* a-priori bound on the relative coefficient error (aliasing of the truncated
+                                  kernel plus deconvolution mismatch), excluding floating-point rounding */
 } mm_plan_info;
 
 /* Plan of a type-1 NUFFT of cutoff N (Sec. 2.2.5): the spreading width follows
- * the paper's tolerance rules (Sec. 2.2.5, with the ES rule's M_sp + 2), the
- * grid is Mr = smallest even 2,3,5-smooth length >= max(sigma(2N+1), 2 width, 8)
- * with sigma = 2 (Sec. 2.2.5), unless `tune` overrides.  Host only. */
+ * the paper's tolerance rules (Sec. 2.2.5, with the ES rule's M_sp + 2) on the
+ * FP64 path and the smallest width meeting tol by the a-priori estimate on the
+ * mixed path; the grid is Mr = smallest even 2,3,5-smooth length
+ * >= max(sigma(2N+1), 2 width, 8) with sigma = 2 (Sec. 2.2.5), unless `tune`
+ * overrides.  Host only. */
 mm_status mm_plan_query(int32_t N, mm_kernel kernel, double tol, mm_prec prec,
                         const mm_tuning* tune, mm_plan_info* out /* host */);
 

@@ -117,6 +117,7 @@ mm_status mm_plan_query(int32_t N, mm_kernel kernel, double tol, mm_prec prec, c
     out->sigma = p.sigma;
     out->beta = kernel == MM_ES ? p.kp.es_beta : (kernel == MM_GAUSSIAN ? p.kp.g_lambda : p.kp.kb_b);
     out->tol = p.tol;
+    out->est_err = p.est_err;
     return MM_OK;
 }
 

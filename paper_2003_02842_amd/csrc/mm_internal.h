@@ -32,6 +32,14 @@ struct FFTDesc {
     int tws[kMaxStages];      // twiddle-table stride n / span of stage s
     FastDiv dm[kMaxStages];   // division by m[s]
     FastDiv dnr[kMaxStages];  // division by n / r[s]
+    // LDS passes: each applies one stage (p2 = 1) or two consecutive stages
+    // (radix p1 then p2) to p1*p2 values a thread keeps in registers.
+    int np;
+    int p1[kMaxStages], p2[kMaxStages];
+    int pm1[kMaxStages], pm2[kMaxStages], plen[kMaxStages];
+    int pts1[kMaxStages], pts2[kMaxStages];
+    FastDiv pdtask[kMaxStages];   // division by n / (p1 p2), tasks per transform
+    FastDiv pdm2[kMaxStages];     // division by tasks per block
 };
 
 // Averaging-kernel parameters in grid units (x = cell distance).
@@ -54,8 +62,11 @@ struct Plan {
     int kernel;          // mm_kernel
     int N, M;            // cutoff and M = 2N + 1
     double tol, sigma;
-    int msp;             // spreading half-width rule value M_sp
+    int msp;             // spreading half-width M_sp of the paper's tolerance rule
+    int wmsp;            // half-width parameter of the kernel actually used
+    double est_err;      // a-priori worst-case relative coefficient error
     int Mr, L, L1, L2;   // real grid length, complex length Mr/2 = L1 * L2
+    int L2p;             // row pitch (complex) of the L1 x L2 grid view: L2 rounded up to 128 bytes
     KernParams kp;
     FFTDesc F1, F2;
     int CB;              // columns per block of the column pass

@@ -44,102 +44,172 @@ template <typename C> __device__ __forceinline__ C cmi(C a) { return C{a.y, -a.x
 // +i * a
 template <typename C> __device__ __forceinline__ C cpi(C a) { return C{-a.y, a.x}; }
 
-// One radix-r butterfly of an in-place DIF stage: base[q*m], q < r, replaced by
-// their r-point DFT (exp(-2 pi i/r)), output q' times W_span^{j q'} = tw[j q' ts].
-template <typename T>
-__device__ __forceinline__ void butterfly(typename CT<T>::type* base, int m, int r, int j, int ts,
-                                          const typename CT<T>::type* tw)
+// In-place forward DFT of R values (R = 2, 3, 4, 5), exp(-2 pi i/R).
+template <typename T, int R>
+__device__ __forceinline__ void dft(typename CT<T>::type* v)
 {
     using C = typename CT<T>::type;
-    if (r == 4) {
-        C x0 = base[0], x1 = base[m], x2 = base[2 * m], x3 = base[3 * m];
-        C a = cadd(x0, x2), b = csub(x0, x2), c = cadd(x1, x3), d = csub(x1, x3);
-        C y0 = cadd(a, c), y2 = csub(a, c), y1 = cadd(b, cmi(d)), y3 = cadd(b, cpi(d));
-        if (j) {
-            y1 = cmul(y1, tw[j * ts]);
-            y2 = cmul(y2, tw[2 * j * ts]);
-            y3 = cmul(y3, tw[3 * j * ts]);
-        }
-        base[0] = y0; base[m] = y1; base[2 * m] = y2; base[3 * m] = y3;
-    } else if (r == 5) {
+    if constexpr (R == 2) {
+        C a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    } else if constexpr (R == 3) {
+        const T s3 = (T)0.86602540378443864676;
+        C t1 = cadd(v[1], v[2]);
+        C t2 = C{v[0].x - (T)0.5 * t1.x, v[0].y - (T)0.5 * t1.y};
+        C t3 = cscale(csub(v[1], v[2]), s3);
+        v[0] = cadd(v[0], t1);
+        v[1] = cadd(t2, cmi(t3));
+        v[2] = cadd(t2, cpi(t3));
+    } else if constexpr (R == 4) {
+        C a = cadd(v[0], v[2]), b = csub(v[0], v[2]), c = cadd(v[1], v[3]), d = csub(v[1], v[3]);
+        v[0] = cadd(a, c);
+        v[2] = csub(a, c);
+        v[1] = cadd(b, cmi(d));
+        v[3] = cadd(b, cpi(d));
+    } else {
         const T c1 = (T)0.30901699437494742410, c2 = (T)-0.80901699437494742410;
         const T s1 = (T)0.95105651629515357212, s2 = (T)0.58778525229247312917;
-        C x0 = base[0], x1 = base[m], x2 = base[2 * m], x3 = base[3 * m], x4 = base[4 * m];
-        C a1 = cadd(x1, x4), b1 = csub(x1, x4), a2 = cadd(x2, x3), b2 = csub(x2, x3);
-        C y0 = cadd(x0, cadd(a1, a2));
+        C x0 = v[0];
+        C a1 = cadd(v[1], v[4]), b1 = csub(v[1], v[4]), a2 = cadd(v[2], v[3]), b2 = csub(v[2], v[3]);
         C p1 = C{x0.x + c1 * a1.x + c2 * a2.x, x0.y + c1 * a1.y + c2 * a2.y};
         C q1 = C{s1 * b1.x + s2 * b2.x, s1 * b1.y + s2 * b2.y};
         C p2 = C{x0.x + c2 * a1.x + c1 * a2.x, x0.y + c2 * a1.y + c1 * a2.y};
         C q2 = C{s2 * b1.x - s1 * b2.x, s2 * b1.y - s1 * b2.y};
-        C y1 = cadd(p1, cmi(q1)), y4 = cadd(p1, cpi(q1));
-        C y2 = cadd(p2, cmi(q2)), y3 = cadd(p2, cpi(q2));
-        if (j) {
-            y1 = cmul(y1, tw[j * ts]);
-            y2 = cmul(y2, tw[2 * j * ts]);
-            y3 = cmul(y3, tw[3 * j * ts]);
-            y4 = cmul(y4, tw[4 * j * ts]);
-        }
-        base[0] = y0; base[m] = y1; base[2 * m] = y2; base[3 * m] = y3; base[4 * m] = y4;
-    } else if (r == 3) {
-        const T s3 = (T)0.86602540378443864676;
-        C x0 = base[0], x1 = base[m], x2 = base[2 * m];
-        C t1 = cadd(x1, x2);
-        C t2 = C{x0.x - (T)0.5 * t1.x, x0.y - (T)0.5 * t1.y};
-        C t3 = cscale(csub(x1, x2), s3);
-        C y0 = cadd(x0, t1), y1 = cadd(t2, cmi(t3)), y2 = cadd(t2, cpi(t3));
-        if (j) {
-            y1 = cmul(y1, tw[j * ts]);
-            y2 = cmul(y2, tw[2 * j * ts]);
-        }
-        base[0] = y0; base[m] = y1; base[2 * m] = y2;
-    } else {
-        C x0 = base[0], x1 = base[m];
-        C y1 = csub(x0, x1);
-        if (j) y1 = cmul(y1, tw[j * ts]);
-        base[0] = cadd(x0, x1); base[m] = y1;
+        v[0] = cadd(x0, cadd(a1, a2));
+        v[1] = cadd(p1, cmi(q1));
+        v[4] = cadd(p1, cpi(q1));
+        v[2] = cadd(p2, cmi(q2));
+        v[3] = cadd(p2, cpi(q2));
     }
 }
 
-// nb independent length-n transforms, transform b at buf + b*ldb (unit stride).
+// One task of an LDS pass: the R1*R2 values base[q1 m1 + q2 m2] go through
+// DIF stage A (radix R1, span len = R1 m1, butterfly index j = j2 + q2 m2,
+// output q1' times W_len^{j q1'}) and, if R2 > 1, stage B on each of the R1
+// sub-blocks (radix R2, span m1, butterfly index j2, output q2' times
+// W_m1^{j2 q2'}), all in registers.  tw[i] = W_n^i, ts1 = n/len, ts2 = n/m1.
+template <typename T, int R1, int R2>
+__device__ __forceinline__ void pass_task(typename CT<T>::type* base, int m1, int m2, int j2, int ts1, int ts2,
+                                          const typename CT<T>::type* tw)
+{
+    using C = typename CT<T>::type;
+    C x[R1][R2];
+#pragma unroll
+    for (int a = 0; a < R1; ++a)
+#pragma unroll
+        for (int b = 0; b < R2; ++b) x[a][b] = base[a * m1 + b * m2];
+#pragma unroll
+    for (int b = 0; b < R2; ++b) {
+        C v[R1];
+#pragma unroll
+        for (int a = 0; a < R1; ++a) v[a] = x[a][b];
+        dft<T, R1>(v);
+        const int j = j2 + b * m2;
+        if (j) {
+#pragma unroll
+            for (int a = 1; a < R1; ++a) v[a] = cmul(v[a], tw[j * a * ts1]);
+        }
+#pragma unroll
+        for (int a = 0; a < R1; ++a) x[a][b] = v[a];
+    }
+    if constexpr (R2 > 1) {
+#pragma unroll
+        for (int a = 0; a < R1; ++a) {
+            C v[R2];
+#pragma unroll
+            for (int b = 0; b < R2; ++b) v[b] = x[a][b];
+            dft<T, R2>(v);
+            if (j2) {
+#pragma unroll
+                for (int b = 1; b < R2; ++b) v[b] = cmul(v[b], tw[j2 * b * ts2]);
+            }
+#pragma unroll
+            for (int b = 0; b < R2; ++b) x[a][b] = v[b];
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < R1; ++a)
+#pragma unroll
+        for (int b = 0; b < R2; ++b) base[a * m1 + b * m2] = x[a][b];
+}
+
+template <typename T, int R1>
+__device__ __forceinline__ void pass_task_r2(int r2, typename CT<T>::type* base, int m1, int m2, int j2, int ts1,
+                                             int ts2, const typename CT<T>::type* tw)
+{
+    switch (r2) {
+        case 1: pass_task<T, R1, 1>(base, m1, m2, j2, ts1, ts2, tw); break;
+        case 2: pass_task<T, R1, 2>(base, m1, m2, j2, ts1, ts2, tw); break;
+        case 3: pass_task<T, R1, 3>(base, m1, m2, j2, ts1, ts2, tw); break;
+        case 4: pass_task<T, R1, 4>(base, m1, m2, j2, ts1, ts2, tw); break;
+        default: pass_task<T, R1, 5>(base, m1, m2, j2, ts1, ts2, tw); break;
+    }
+}
+
+// nb independent length-n transforms, transform b at buf + b*ldb (unit stride),
+// in place by decimation in frequency; the output sits in digit-reversed order.
 // tw holds W_n^j = exp(-2 pi i j/n), j < n.  Ends with a barrier.
 template <typename T>
 __device__ void fft_lds(typename CT<T>::type* buf, int ldb, int nb, const FFTDesc& F,
                         const typename CT<T>::type* tw)
 {
-    for (int s = 0; s < F.ns; ++s) {
-        const int r = F.r[s], m = F.m[s], ts = F.tws[s];
-        const int nr = (int)F.dnr[s].d, len = m * r;
-        const int total = nb * nr;
+    for (int q = 0; q < F.np; ++q) {
+        const int r1 = F.p1[q], r2 = F.p2[q], m1 = F.pm1[q], m2 = F.pm2[q], len = F.plen[q];
+        const int ts1 = F.pts1[q], ts2 = F.pts2[q];
+        const int tasks = (int)F.pdtask[q].d;
+        const int total = nb * tasks;
         for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-            int b = (int)fdiv((uint32_t)idx, F.dnr[s]);
-            int bf = idx - b * nr;
-            int blk = (int)fdiv((uint32_t)bf, F.dm[s]);
-            int j = bf - blk * m;
-            butterfly<T>(buf + b * ldb + blk * len + j, m, r, j, ts, tw);
+            const int b = (int)fdiv((uint32_t)idx, F.pdtask[q]);
+            const int tsk = idx - b * tasks;
+            const int blk = (int)fdiv((uint32_t)tsk, F.pdm2[q]);
+            const int j2 = tsk - blk * m2;
+            typename CT<T>::type* base = buf + b * ldb + blk * len + j2;
+            switch (r1) {
+                case 2: pass_task_r2<T, 2>(r2, base, m1, m2, j2, ts1, ts2, tw); break;
+                case 3: pass_task_r2<T, 3>(r2, base, m1, m2, j2, ts1, ts2, tw); break;
+                case 4: pass_task_r2<T, 4>(r2, base, m1, m2, j2, ts1, ts2, tw); break;
+                default: pass_task_r2<T, 5>(r2, base, m1, m2, j2, ts1, ts2, tw); break;
+            }
         }
         __syncthreads();
     }
 }
 
 // ------------------------------------------------------------------------------------------
-// Time -> grid reduction (FP64).  u = (t - t0)/(T - t0); g = u Mr formed exactly as
-// p + e (two-product); first tap l0 = floor(g - hw) + 1 and fraction f = frac(g - hw),
-// so tap j sits at cell l0 + j at kernel argument x_j = j + 1 - f - hw in (-hw, hw].
-// The key l0 is nondecreasing in t, which the per-tile binary searches rely on.
-template <bool EXACT_DIV>
-__device__ __forceinline__ void cell_of(double t, double t0, double span, double inv_span, int Mr, double hw,
+// Time -> grid reduction (FP64).  u = (t - t0)/(T - t0), g = u Mr; first tap
+// l0 = floor(g - hw) + 1 and fraction f = frac(g - hw), so tap j sits at cell
+// l0 + j at kernel argument x_j = j + 1 - f - hw in (-hw, hw].  The key l0 is
+// nondecreasing in t, which the per-tile binary searches rely on.  On the FP64
+// path g is formed exactly as p + e (two-product).
+//
+// The mixed path (EXACT = false) needs the cell position only to ~1e-9 cells (it
+// becomes an FP32 offset), so it forms g = (t - t0) (Mr/(T - t0)) with ordinary
+// FP64 rounding; the FP64 path divides exactly like the definition and keeps the
+// error-free product.  Either form is monotone in t.
+template <bool EXACT>
+__device__ __forceinline__ void cell_of(double t, double t0, double span, double scale, int Mr, double hw,
                                         int64_t& l0, double& f)
 {
-    double u = EXACT_DIV ? (t - t0) / span : (t - t0) * inv_span;
-    double p = u * (double)Mr;
-    double e = fma(u, (double)Mr, -p);
-    double tt = p - hw;
-    double fl = floor(tt);
-    double fr = (tt - fl) + e;
-    if (fr < 0.0) { fl -= 1.0; fr += 1.0; }
-    if (fr >= 1.0) { fl += 1.0; fr -= 1.0; }
-    l0 = (int64_t)fl + 1;
-    f = fr;
+    // Explicitly rounded operations: the tile-range search and the spreading must
+    // compute bit-identical keys, so no contraction may differ between them.
+    if (EXACT) {
+        double u = __ddiv_rn(__dsub_rn(t, t0), span);
+        double p = __dmul_rn(u, (double)Mr);
+        double e = fma(u, (double)Mr, -p);
+        double tt = __dsub_rn(p, hw);
+        double fl = floor(tt);
+        double fr = __dadd_rn(__dsub_rn(tt, fl), e);
+        if (fr < 0.0) { fl -= 1.0; fr += 1.0; }
+        if (fr >= 1.0) { fl += 1.0; fr -= 1.0; }
+        l0 = (int64_t)fl + 1;
+        f = fr;
+    } else {
+        double tt = fma(__dsub_rn(t, t0), scale, -hw);
+        double fl = floor(tt);
+        l0 = (int64_t)fl + 1;
+        f = __dsub_rn(tt, fl);
+    }
 }
 
 __device__ __forceinline__ float fexp2(float x) { return __builtin_amdgcn_exp2f(x); }
@@ -212,7 +282,7 @@ __device__ __forceinline__ T kern_eval(T x, const KEval<T>& k)
 template <bool EXACT_DIV>
 __global__ void k_tile_ranges(const int64_t* __restrict__ offsets, const double* __restrict__ t, int s_begin,
                               int s_count, int tiles, int tc, int Mr, int w, double hw, double t0, double span,
-                              double inv_span, int64_t* __restrict__ ranges)
+                              double scale, int64_t* __restrict__ ranges)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)s_count * tiles * 6) return;
@@ -229,7 +299,7 @@ __global__ void k_tile_ranges(const int64_t* __restrict__ offsets, const double*
         const int64_t mid = (lo + hi) >> 1;
         int64_t l0;
         double f;
-        cell_of<EXACT_DIV>(t[mid], t0, span, inv_span, Mr, hw, l0, f);
+        cell_of<EXACT_DIV>(t[mid], t0, span, scale, Mr, hw, l0, f);
         if (l0 < key) lo = mid + 1;
         else hi = mid;
     }
@@ -250,13 +320,14 @@ struct EvRec {
 // [c, c + w - 1].  No atomics: each grid value is one thread's register sum.
 template <typename T, typename DPT, int KIND, int CPT>
 __global__ __launch_bounds__(256) void k_spread(const double* __restrict__ t, const DPT* __restrict__ dp,
-                                                double t0, double span, double inv_span, KernParams kp, int Mr,
-                                                const int64_t* __restrict__ ranges, int tiles,
-                                                T* __restrict__ grid, int64_t grid_stride)
+                                                double t0, double span, double scale, KernParams kp, int Mr,
+                                                const int64_t* __restrict__ ranges, int tiles, int L2, int L2p,
+                                                FastDiv divL2, T* __restrict__ grid, int64_t grid_stride)
 {
-    constexpr bool EXACT_DIV = sizeof(T) == 8;
+    constexpr bool EXACT = sizeof(T) == 8;
     constexpr int TC = 256 * CPT;
     constexpr int EC = sizeof(T) == 4 ? 2048 : 1024;
+    constexpr int SB = EC / 256;   // events per thread per chunk
     __shared__ EvRec<T> ev[EC];
     __shared__ unsigned short first[TC + kMaxTaps + 2];
     const int a = blockIdx.x * TC;
@@ -264,64 +335,114 @@ __global__ __launch_bounds__(256) void k_spread(const double* __restrict__ t, co
     const int w = kp.w;
     const KEval<T> ke(kp);
     const int64_t* rg = ranges + ((int64_t)blockIdx.y * tiles + blockIdx.x) * 6;
+    // The three key ranges (m = -1, 0, 1) as one list of chunks of EC events.
+    int64_t rb[3], nchunk[3];
+    int total_chunks = 0;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        rb[m] = rg[2 * m];
+        const int64_t ne = rg[2 * m + 1] - rb[m];
+        nchunk[m] = (ne + EC - 1) / EC;
+        total_chunks += (int)nchunk[m];
+    }
+    auto locate = [&](int q, int64_t& cb, int& n, int& m) {
+        m = 0;
+        while (q >= nchunk[m]) { q -= (int)nchunk[m]; ++m; }
+        cb = rb[m] + (int64_t)q * EC;
+        n = (int)min((int64_t)EC, rg[2 * m + 1] - cb);
+    };
     T acc[CPT];
 #pragma unroll
     for (int r = 0; r < CPT; ++r) acc[r] = (T)0;
-    for (int mi = 0; mi < 3; ++mi) {
-        const int64_t b0 = rg[2 * mi], b1 = rg[2 * mi + 1];
-        const int64_t shift = (int64_t)a + (int64_t)(mi - 1) * Mr;
-        for (int64_t cb = b0; cb < b1; cb += EC) {
-            const int n = (int)min((int64_t)EC, b1 - cb);
-            __syncthreads();
-            for (int i = threadIdx.x; i < n; i += 256) {
+    double tv[SB];
+    DPT dv[SB];
+    if (total_chunks > 0) {
+        int64_t cb; int n, m;
+        locate(0, cb, n, m);
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+            const int i = (int)threadIdx.x + 256 * u;
+            if (i < n) { tv[u] = t[cb + i]; dv[u] = dp[cb + i]; }
+        }
+    }
+    for (int q = 0; q < total_chunks; ++q) {
+        int64_t cb; int n, m;
+        locate(q, cb, n, m);
+        const int64_t shift = (int64_t)a + (int64_t)(m - 1) * Mr;
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+            const int i = (int)threadIdx.x + 256 * u;
+            if (i < n) {
                 int64_t l0;
                 double f;
-                cell_of<EXACT_DIV>(t[cb + i], t0, span, inv_span, Mr, kp.hw, l0, f);
+                cell_of<EXACT>(tv[u], t0, span, scale, Mr, kp.hw, l0, f);
                 EvRec<T> r;
                 r.key = (int)(l0 - shift) + w - 1;
                 r.x0 = (T)(1.0 - f - kp.hw);
-                r.v = (T)dp[cb + i];
+                r.v = (T)dv[u];
                 ev[i] = r;
             }
-            __syncthreads();
-            const int kmin = ev[0].key, kmax = ev[n - 1].key;
-            for (int i = 1 + threadIdx.x; i < n; i += 256) {
-                const int k1 = ev[i].key;
-                for (int k = ev[i - 1].key + 1; k <= k1; ++k) first[k] = (unsigned short)i;
-            }
-            __syncthreads();
+        }
+        // prefetch the next chunk while this one is summed
+        if (q + 1 < total_chunks) {
+            int64_t cb2; int n2, m2;
+            locate(q + 1, cb2, n2, m2);
 #pragma unroll
-            for (int r = 0; r < CPT; ++r) {
-                const int c = threadIdx.x + 256 * r;
-                if (c >= len || c + w - 1 < kmin || c > kmax) continue;
-                const int lo = (c <= kmin) ? 0 : first[c];
-                const int hi = (c + w > kmax) ? n : first[c + w];
-                const int cw = c + w - 1;
-                T s0 = (T)0, s1 = (T)0;
-                int e = lo;
-                for (; e + 1 < hi; e += 2) {
-                    const EvRec<T> p = ev[e], q = ev[e + 1];
-                    s0 += p.v * kern_eval<T, KIND>((T)(cw - p.key) + p.x0, ke);
-                    s1 += q.v * kern_eval<T, KIND>((T)(cw - q.key) + q.x0, ke);
-                }
-                if (e < hi) {
-                    const EvRec<T> p = ev[e];
-                    s0 += p.v * kern_eval<T, KIND>((T)(cw - p.key) + p.x0, ke);
-                }
-                acc[r] += s0 + s1;
+            for (int u = 0; u < SB; ++u) {
+                const int i = (int)threadIdx.x + 256 * u;
+                if (i < n2) { tv[u] = t[cb2 + i]; dv[u] = dp[cb2 + i]; }
             }
         }
+        __syncthreads();
+        const int kmin = ev[0].key, kmax = ev[n - 1].key;
+        for (int i = 1 + threadIdx.x; i < n; i += 256) {
+            const int k1 = ev[i].key;
+            for (int k = ev[i - 1].key + 1; k <= k1; ++k) first[k] = (unsigned short)i;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < CPT; ++r) {
+            const int c = threadIdx.x + 256 * r;
+            if (c >= len || c + w - 1 < kmin || c > kmax) continue;
+            const int lo = (c <= kmin) ? 0 : first[c];
+            const int hi = (c + w > kmax) ? n : first[c + w];
+            const int cw = c + w - 1;
+            T s0 = (T)0, s1 = (T)0;
+            int e = lo;
+            for (; e + 1 < hi; e += 2) {
+                const EvRec<T> p = ev[e], q2 = ev[e + 1];
+                s0 += p.v * kern_eval<T, KIND>((T)(cw - p.key) + p.x0, ke);
+                s1 += q2.v * kern_eval<T, KIND>((T)(cw - q2.key) + q2.x0, ke);
+            }
+            if (e < hi) {
+                const EvRec<T> p = ev[e];
+                s0 += p.v * kern_eval<T, KIND>((T)(cw - p.key) + p.x0, ke);
+            }
+            acc[r] += s0 + s1;
+        }
     }
-    T* out = grid + (int64_t)blockIdx.y * grid_stride + a;
+    // real cell a + c is part (a + c) & 1 of complex entry j = (a + c) >> 1, which the
+    // L1 x L2 view stores at row j / L2, column j % L2, rows L2p apart
+    T* out = grid + (int64_t)blockIdx.y * grid_stride;
 #pragma unroll
     for (int r = 0; r < CPT; ++r) {
         const int c = threadIdx.x + 256 * r;
-        if (c < len) out[c] = acc[r];
+        if (c < len) {
+            const int cell = a + c, j = cell >> 1;
+            const int row = (int)fdiv((uint32_t)j, divL2);
+            out[2 * ((int64_t)row * L2p + (j - row * L2)) + (cell & 1)] = acc[r];
+        }
     }
 }
 
+constexpr int kBatch = 8;   // independent global loads a thread issues before consuming them
+
+// First FFT pass, in place on the packed complex grid viewed as an L1 x L2
+// row-major matrix: workgroup (column block, series) transforms CB columns of
+// length L1 and multiplies entry (k1, l2) by W_L^{k1 l2}.
 template <typename T>
-__global__ __launch_bounds__(256) void k_fft_cols(T* __restrict__ grid, int64_t grid_stride, int L1, int L2,
+__global__ __launch_bounds__(256) void k_fft_cols(T* __restrict__ grid, int64_t grid_stride, int L1, int L2, int L2p,
                                                   int cb_shift, FFTDesc F1, const typename CT<T>::type* __restrict__ tw1,
                                                   const typename CT<T>::type* __restrict__ twL,
                                                   const int* __restrict__ rev1)
@@ -329,32 +450,61 @@ __global__ __launch_bounds__(256) void k_fft_cols(T* __restrict__ grid, int64_t 
     using C = typename CT<T>::type;
     extern __shared__ __align__(16) char smem_raw[];
     C* tws = reinterpret_cast<C*>(smem_raw);
-    C* buf = tws + L1;
+    int* rev = reinterpret_cast<int*>(tws + L1);
+    C* buf = reinterpret_cast<C*>(rev + ((L1 + 3) & ~3));
     const int CB = 1 << cb_shift;
     const int ldb = L1 | 1;
     C* z = reinterpret_cast<C*>(grid + (int64_t)blockIdx.y * grid_stride);
     const int c0 = blockIdx.x * CB;
     const int nb = min(CB, L2 - c0);
-    for (int i = threadIdx.x; i < L1; i += blockDim.x) tws[i] = tw1[i];
-    for (int idx = threadIdx.x; idx < L1 * CB; idx += blockDim.x) {
-        int l1 = idx >> cb_shift, b = idx & (CB - 1);
-        if (b < nb) buf[b * ldb + l1] = z[(int64_t)l1 * L2 + c0 + b];
+    for (int i = threadIdx.x; i < L1; i += blockDim.x) {
+        tws[i] = tw1[i];
+        rev[i] = rev1[i];
+    }
+    const int total = L1 * CB;
+    for (int base = 0; base < total; base += 256 * kBatch) {
+        C v[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int idx = base + u * 256 + (int)threadIdx.x;
+            const int l1 = idx >> cb_shift, b = idx & (CB - 1);
+            if (idx < total && b < nb) v[u] = z[(int64_t)l1 * L2p + c0 + b];
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int idx = base + u * 256 + (int)threadIdx.x;
+            const int l1 = idx >> cb_shift, b = idx & (CB - 1);
+            if (idx < total && b < nb) buf[b * ldb + l1] = v[u];
+        }
     }
     __syncthreads();
     fft_lds<T>(buf, ldb, nb, F1, tws);
-    for (int idx = threadIdx.x; idx < L1 * CB; idx += blockDim.x) {
-        int p = idx >> cb_shift, b = idx & (CB - 1);
-        if (b < nb) {
-            int k1 = rev1[p];
-            C v = cmul(buf[b * ldb + p], twL[(int64_t)(c0 + b) * k1]);
-            z[(int64_t)k1 * L2 + c0 + b] = v;
+    for (int base = 0; base < total; base += 256 * kBatch) {
+        C tv[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int idx = base + u * 256 + (int)threadIdx.x;
+            const int p = idx >> cb_shift, b = idx & (CB - 1);
+            if (idx < total && b < nb) tv[u] = twL[(int64_t)(c0 + b) * rev[p]];
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int idx = base + u * 256 + (int)threadIdx.x;
+            const int p = idx >> cb_shift, b = idx & (CB - 1);
+            if (idx < total && b < nb) z[(int64_t)rev[p] * L2p + c0 + b] = cmul(buf[b * ldb + p], tv[u]);
         }
     }
 }
 
+// Second FFT pass: workgroup (row-pair block, series) loads rows k1 and
+// L1 - k1 (mod L1) for R consecutive k1, transforms them (length L2), and writes
+// c_k for k = k1 + L1 k2 <= N: the real-input untangling
+//   X_k = (Z_k + conj Z_{L-k})/2 - (i/2) W_Mr^k (Z_k - conj Z_{L-k})
+// (Z_{L-k} sits in the mirror row), then the deconvolution factor.
 template <typename T>
-__global__ __launch_bounds__(256) void k_fft_rows(const T* __restrict__ grid, int64_t grid_stride, int L1, int L2,
-                                                  int r_shift, FFTDesc F2, const typename CT<T>::type* __restrict__ tw2,
+__global__ __launch_bounds__(256) void k_fft_rows(const T* __restrict__ grid, int64_t grid_stride, int L1, int L2, int L2p,
+                                                  int r_shift, FFTDesc F2, FastDiv divL2,
+                                                  const typename CT<T>::type* __restrict__ tw2,
                                                   const int* __restrict__ pos2, const typename CT<T>::type* __restrict__ twM,
                                                   const T* __restrict__ dfac, int N, typename CT<T>::type* __restrict__ coef,
                                                   int64_t ldc, int s_out)
@@ -362,7 +512,8 @@ __global__ __launch_bounds__(256) void k_fft_rows(const T* __restrict__ grid, in
     using C = typename CT<T>::type;
     extern __shared__ __align__(16) char smem_raw[];
     C* tws = reinterpret_cast<C*>(smem_raw);
-    C* buf = tws + L2;
+    int* pos = reinterpret_cast<int*>(tws + L2);
+    C* buf = reinterpret_cast<C*>(pos + ((L2 + 3) & ~3));
     const int R = 1 << r_shift;
     const int ldb = L2 | 1;
     const C* Y = reinterpret_cast<const C*>(grid + (int64_t)blockIdx.y * grid_stride);
@@ -370,37 +521,74 @@ __global__ __launch_bounds__(256) void k_fft_rows(const T* __restrict__ grid, in
     const int P = L1 / 2 + 1;
     const int p0 = blockIdx.x * R;
     const int nr = min(R, P - p0);
-    for (int i = threadIdx.x; i < L2; i += blockDim.x) tws[i] = tw2[i];
+    for (int i = threadIdx.x; i < L2; i += blockDim.x) {
+        tws[i] = tw2[i];
+        pos[i] = pos2[i];
+    }
     // LDS row 2i holds matrix row p0+i, row 2i+1 its mirror (L1 - p0 - i) mod L1.
-    for (int i = 0; i < 2 * nr; ++i) {
-        const int p = p0 + (i >> 1);
-        const int k1 = (i & 1) ? (L1 - p) % L1 : p;
-        const C* src = Y + (int64_t)k1 * L2;
-        for (int j = threadIdx.x; j < L2; j += blockDim.x) buf[i * ldb + j] = src[j];
+    const int total_in = 2 * nr * L2;
+    for (int base = 0; base < total_in; base += 256 * kBatch) {
+        C v[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int idx = base + u * 256 + (int)threadIdx.x;
+            if (idx < total_in) {
+                const int row = (int)fdiv((uint32_t)idx, divL2), j = idx - row * L2;
+                const int p = p0 + (row >> 1);
+                const int k1 = (row & 1) ? (L1 - p) % L1 : p;
+                v[u] = Y[(int64_t)k1 * L2p + j];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int idx = base + u * 256 + (int)threadIdx.x;
+            if (idx < total_in) {
+                const int row = (int)fdiv((uint32_t)idx, divL2), j = idx - row * L2;
+                buf[row * ldb + j] = v[u];
+            }
+        }
     }
     __syncthreads();
     fft_lds<T>(buf, ldb, 2 * nr, F2, tws);
     const int total = 2 * R * L2;
-    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-        const int i = idx & (R - 1);
-        const int t2 = idx >> r_shift;
-        const int side = t2 & 1, k2 = t2 >> 1;
-        if (i >= nr) continue;
-        const int p = p0 + i;
-        const int rowA = p, rowB = (L1 - p) % L1;
-        if (side && rowB == rowA) continue;
-        const int k1 = side ? rowB : rowA;
-        const int64_t k = (int64_t)k1 + (int64_t)L1 * k2;
-        if (k > N) continue;
-        const int k2m = (k1 == 0) ? (k2 == 0 ? 0 : L2 - k2) : (L2 - 1 - k2);
-        const C Zk = buf[(2 * i + side) * ldb + pos2[k2]];
-        const C Zm = buf[(2 * i + 1 - side) * ldb + pos2[k2m]];
-        // X_k = (Z_k + conj Z_{L-k})/2 - (i/2) W_Mr^k (Z_k - conj Z_{L-k})
-        const C A = C{Zk.x + Zm.x, Zk.y - Zm.y};
-        const C B = C{Zk.x - Zm.x, Zk.y + Zm.y};
-        const C WB = cmul(twM[k], B);
-        const T d = dfac[k] * (T)0.5;
-        out[k] = C{(A.x + WB.y) * d, (A.y - WB.x) * d};
+    for (int base = 0; base < total; base += 256 * kBatch) {
+        C wk[kBatch];
+        T dk[kBatch];
+        int64_t kk[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int idx = base + u * 256 + (int)threadIdx.x;
+            const int i = idx & (R - 1);
+            const int t2 = idx >> r_shift;
+            const int side = t2 & 1, k2 = t2 >> 1;
+            const int p = p0 + i;
+            const int rowA = p, rowB = (L1 - p) % L1;
+            const int k1 = side ? rowB : rowA;
+            const int64_t k = (int64_t)k1 + (int64_t)L1 * k2;
+            const bool ok = idx < total && i < nr && !(side && rowB == rowA) && k <= N;
+            kk[u] = ok ? k : -1;
+            if (ok) {
+                wk[u] = twM[k];
+                dk[u] = dfac[k];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            if (kk[u] < 0) continue;
+            const int idx = base + u * 256 + (int)threadIdx.x;
+            const int i = idx & (R - 1);
+            const int t2 = idx >> r_shift;
+            const int side = t2 & 1, k2 = t2 >> 1;
+            const int k1 = (int)(kk[u] - (int64_t)L1 * k2);
+            const int k2m = (k1 == 0) ? (k2 == 0 ? 0 : L2 - k2) : (L2 - 1 - k2);
+            const C Zk = buf[(2 * i + side) * ldb + pos[k2]];
+            const C Zm = buf[(2 * i + 1 - side) * ldb + pos[k2m]];
+            const C A = C{Zk.x + Zm.x, Zk.y - Zm.y};
+            const C B = C{Zk.x - Zm.x, Zk.y + Zm.y};
+            const C WB = cmul(wk[u], B);
+            const T d = dk[u] * (T)0.5;
+            out[kk[u]] = C{(A.x + WB.y) * d, (A.y - WB.x) * d};
+        }
     }
 }
 
@@ -560,16 +748,17 @@ static void launch_spread_t(const Plan& p, int s_count, const double* t, const D
                             const int64_t* ranges, int tiles, T* grid, int64_t grid_stride, hipStream_t st)
 {
     const double span = t_end - t0;
+    const double scale = (double)p.Mr / span;
     const dim3 g(tiles, s_count);
     if (p.tile <= 1024)
-        hipLaunchKernelGGL((k_spread<T, DPT, KIND, 4>), g, dim3(256), 0, st, t, dp, t0, span, 1.0 / span, p.kp, p.Mr,
-                           ranges, tiles, grid, grid_stride);
+        hipLaunchKernelGGL((k_spread<T, DPT, KIND, 4>), g, dim3(256), 0, st, t, dp, t0, span, scale, p.kp, p.Mr,
+                           ranges, tiles, p.L2, p.L2p, make_fastdiv((uint32_t)p.L2), grid, grid_stride);
     else if (p.tile <= 2048)
-        hipLaunchKernelGGL((k_spread<T, DPT, KIND, 8>), g, dim3(256), 0, st, t, dp, t0, span, 1.0 / span, p.kp, p.Mr,
-                           ranges, tiles, grid, grid_stride);
+        hipLaunchKernelGGL((k_spread<T, DPT, KIND, 8>), g, dim3(256), 0, st, t, dp, t0, span, scale, p.kp, p.Mr,
+                           ranges, tiles, p.L2, p.L2p, make_fastdiv((uint32_t)p.L2), grid, grid_stride);
     else
-        hipLaunchKernelGGL((k_spread<T, DPT, KIND, 16>), g, dim3(256), 0, st, t, dp, t0, span, 1.0 / span, p.kp,
-                           p.Mr, ranges, tiles, grid, grid_stride);
+        hipLaunchKernelGGL((k_spread<T, DPT, KIND, 16>), g, dim3(256), 0, st, t, dp, t0, span, scale, p.kp,
+                           p.Mr, ranges, tiles, p.L2, p.L2p, make_fastdiv((uint32_t)p.L2), grid, grid_stride);
 }
 
 template <typename T, typename DPT>
@@ -598,7 +787,7 @@ static hipError_t nufft_tiled_t(const Plan& p, const NufftWs& w, char* ws, int32
 {
     using C = typename CT<T>::type;
     T* grid = (T*)(ws + w.grid);
-    const int64_t gstride = p.Mr;
+    const int64_t gstride = 2ll * p.L1 * p.L2p;
     const int tiles = (p.Mr + p.tile - 1) / p.tile;
     int64_t* ranges = (int64_t*)(ws + w.ranges);
     const double span = T_ - t0;
@@ -606,10 +795,10 @@ static hipError_t nufft_tiled_t(const Plan& p, const NufftWs& w, char* ws, int32
     prof_begin("k_tile_ranges", st);
     if (p.prec == MM_PLAIN_FP64)
         hipLaunchKernelGGL(k_tile_ranges<true>, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, st, offsets, t,
-                           s_begin, s_count, tiles, p.tile, p.Mr, p.kp.w, p.kp.hw, t0, span, 1.0 / span, ranges);
+                           s_begin, s_count, tiles, p.tile, p.Mr, p.kp.w, p.kp.hw, t0, span, (double)p.Mr / span, ranges);
     else
         hipLaunchKernelGGL(k_tile_ranges<false>, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, st, offsets, t,
-                           s_begin, s_count, tiles, p.tile, p.Mr, p.kp.w, p.kp.hw, t0, span, 1.0 / span, ranges);
+                           s_begin, s_count, tiles, p.tile, p.Mr, p.kp.w, p.kp.hw, t0, span, (double)p.Mr / span, ranges);
     prof_end("k_tile_ranges", st);
     prof_begin("k_spread", st);
     if (dp_fp64)
@@ -619,19 +808,19 @@ static hipError_t nufft_tiled_t(const Plan& p, const NufftWs& w, char* ws, int32
     prof_end("k_spread", st);
 
     const int cbs = ilog2(p.CB);
-    const size_t lds1 = (size_t)(p.L1 + p.CB * (p.L1 | 1)) * sizeof(C);
+    const size_t lds1 = (size_t)(p.L1 + p.CB * (p.L1 | 1)) * sizeof(C) + (size_t)((p.L1 + 3) & ~3) * 4;
     prof_begin("k_fft_cols", st);
     hipLaunchKernelGGL(k_fft_cols<T>, dim3((p.L2 + p.CB - 1) / p.CB, s_count), dim3(256), lds1, st, grid, gstride,
-                       p.L1, p.L2, cbs, p.F1, (const C*)(ws + w.tw1), (const C*)(ws + w.twL),
+                       p.L1, p.L2, p.L2p, cbs, p.F1, (const C*)(ws + w.tw1), (const C*)(ws + w.twL),
                        (const int*)(ws + w.rev1));
     prof_end("k_fft_cols", st);
 
     const int rs = ilog2(p.R);
     const int P = p.L1 / 2 + 1;
-    const size_t lds2 = (size_t)(p.L2 + 2 * p.R * (p.L2 | 1)) * sizeof(C);
+    const size_t lds2 = (size_t)(p.L2 + 2 * p.R * (p.L2 | 1)) * sizeof(C) + (size_t)((p.L2 + 3) & ~3) * 4;
     prof_begin("k_fft_rows", st);
     hipLaunchKernelGGL(k_fft_rows<T>, dim3((P + p.R - 1) / p.R, s_count), dim3(256), lds2, st, grid, gstride, p.L1,
-                       p.L2, rs, p.F2, (const C*)(ws + w.tw2), (const int*)(ws + w.pos2), (const C*)(ws + w.twM),
+                       p.L2, p.L2p, rs, p.F2, make_fastdiv((uint32_t)p.L2), (const C*)(ws + w.tw2), (const int*)(ws + w.pos2), (const C*)(ws + w.twM),
                        (const T*)(ws + w.dfac), p.N, (C*)coef, ldc, s_begin);
     prof_end("k_fft_rows", st);
     return hipGetLastError();

@@ -5,6 +5,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "mm_internal.h"
 
@@ -59,6 +62,22 @@ static bool make_fft_desc(int n, FFTDesc* F)
         F->dnr[s] = make_fastdiv((uint32_t)(n / rad[s]));
         len = F->m[s];
     }
+    // pair consecutive stages into register-resident double passes
+    F->np = 0;
+    for (int s = 0; s < ns; s += 2) {
+        const int q = F->np++;
+        const bool dbl = s + 1 < ns;
+        const int span = F->m[s] * F->r[s];
+        F->p1[q] = F->r[s];
+        F->p2[q] = dbl ? F->r[s + 1] : 1;
+        F->plen[q] = span;
+        F->pm1[q] = F->m[s];
+        F->pm2[q] = dbl ? F->m[s + 1] : F->m[s];
+        F->pts1[q] = n / span;
+        F->pts2[q] = dbl ? n / F->m[s] : 1;
+        F->pdtask[q] = make_fastdiv((uint32_t)(n / (F->p1[q] * F->p2[q])));
+        F->pdm2[q] = make_fastdiv((uint32_t)F->pm2[q]);
+    }
     return true;
 }
 
@@ -107,6 +126,164 @@ void gauss_legendre_pos(int n_pos, double* x, double* w)
     }
 }
 
+// ------------------------------------------------------------------ error estimate
+// The kernel as the spreading taps evaluate it (cells; taps cover (-hw, hw]).
+static double host_psi(const KernParams& kp, double x)
+{
+    if (kp.kind == MM_ES) {
+        double z = x * kp.es_inv_hw;
+        return exp(kp.es_beta * (sqrt(std::max(1.0 - z * z, 0.0)) - 1.0));
+    }
+    if (kp.kind == MM_GAUSSIAN) return exp(-kp.g_t1 * x * x);
+    double s2 = kp.kb_m * kp.kb_m - x * x;
+    double v;
+    if (s2 > 0) { double q = sqrt(s2); v = sinh(kp.kb_b * q) / q; }
+    else if (s2 < 0) { double q = sqrt(-s2); v = sin(kp.kb_b * q) / q; }
+    else v = kp.kb_b;
+    return v * kp.kb_inv_norm;
+}
+
+static double host_i0(double x)
+{
+    double q = 0.25 * x * x, term = 1.0, sum = 1.0;
+    for (int j = 1; j < 1000; ++j) {
+        term *= q / ((double)j * (double)j);
+        sum += term;
+        if (term < 1e-17 * sum) break;
+    }
+    return sum;
+}
+
+// Fourier transform at nu (cycles per cell) of the kernel truncated to the taps'
+// support: 2 int_0^hw psi(x) cos(2 pi nu x) dx, composite 16-point Gauss-Legendre.
+static double host_psihat_trunc(const KernParams& kp, double nu)
+{
+    static double gx[8], gw[8];
+    static bool init = false;
+    if (!init) { gauss_legendre_pos(8, gx, gw); init = true; }
+    const int panels = 32;
+    const double h = kp.hw / panels;
+    double tot = 0.0;
+    for (int q = 0; q < panels; ++q) {
+        const double c = (q + 0.5) * h, r = 0.5 * h;
+        for (int i = 0; i < 8; ++i)
+            for (int sgn = -1; sgn <= 1; sgn += 2) {
+                double x = c + sgn * r * gx[i];
+                tot += r * gw[i] * host_psi(kp, x) * cos(2.0 * kPi * nu * x);
+            }
+    }
+    return 2.0 * tot;
+}
+
+// What the deconvolution divides by (same formulas as the device factors).
+static double host_psihat_deconv(const KernParams& kp, double nu)
+{
+    if (kp.kind == MM_GAUSSIAN) return sqrt(kp.g_lambda) * exp(-kPi * kp.g_lambda * nu * nu);
+    if (kp.kind == MM_KAISER_BESSEL) {
+        double a = kp.kb_b * kp.kb_b - (2.0 * kPi * nu) * (2.0 * kPi * nu);
+        return kPi * kp.kb_inv_norm * host_i0(kp.kb_m * sqrt(std::max(a, 0.0)));
+    }
+    static double gx[kGLNodes], gw[kGLNodes];
+    static bool init = false;
+    if (!init) { gauss_legendre_pos(kGLNodes, gx, gw); init = true; }
+    double acc = 0.0;
+    for (int q = 0; q < kGLNodes; ++q)
+        acc += gw[q] * exp(kp.es_beta * (sqrt(1.0 - gx[q] * gx[q]) - 1.0)) * cos(2.0 * kPi * nu * kp.hw * gx[q]);
+    return 2.0 * kp.hw * acc;
+}
+
+// Worst-case relative error of a coefficient, over k in [0, N]: the aliased
+// images sum_{m != 0} |psi_hat(k/Mr + m)| of the truncated kernel (Poisson
+// summation of the periodic grid, Eqs. Der:14-16) plus the mismatch between the
+// truncated kernel's transform and the factor the deconvolution divides by,
+// both relative to that factor.  Bounds the l2 error of Eq. Der:18.
+static double estimate_error_uncached(const KernParams& kp, int Mr, int N)
+{
+    double worst = 0.0;
+    const int samples = 17;
+    for (int i = 0; i < samples; ++i) {
+        const double k = (double)N * i / (samples - 1);
+        const double nu = k / Mr;
+        const double den = host_psihat_deconv(kp, nu);
+        double ali = 0.0;
+        for (int m = 1; m <= 3; ++m)
+            ali += fabs(host_psihat_trunc(kp, nu + m)) + fabs(host_psihat_trunc(kp, nu - m));
+        const double mis = fabs(host_psihat_trunc(kp, nu) - den);
+        worst = std::max(worst, (ali + mis) / fabs(den));
+    }
+    return worst;
+}
+
+static std::mutex g_est_mu;
+static std::map<std::tuple<int, int, long long, long long, int, int>, double> g_est_cache;
+
+static double estimate_error(const KernParams& kp, double sigma, int Mr, int N)
+{
+    auto key = std::make_tuple(kp.kind, kp.w, (long long)llround(sigma * 1e6), (long long)llround(kp.es_beta * 1e6),
+                               Mr, N);
+    {
+        std::lock_guard<std::mutex> lk(g_est_mu);
+        auto it = g_est_cache.find(key);
+        if (it != g_est_cache.end()) return it->second;
+    }
+    double e = estimate_error_uncached(kp, Mr, N);
+    std::lock_guard<std::mutex> lk(g_est_mu);
+    g_est_cache[key] = e;
+    return e;
+}
+
+// Kernel shape for a width w (taps per event) at oversampling sg.
+static void set_kernel(KernParams& kp, int kernel, int w, int msp, double sg, const mm_tuning* tune)
+{
+    memset(&kp, 0, sizeof(kp));
+    kp.kind = kernel;
+    kp.w = w;
+    kp.hw = 0.5 * w;
+    if (kernel == MM_ES) {
+        // beta = 2.3 omega at sigma = 2 (Eq. Der:10-11); other sigma scale it by (1 - 1/(2 sigma)) / (3/4)
+        double bpt = (tune && tune->es_beta_per_tap > 0) ? tune->es_beta_per_tap : 2.3 * (1.0 - 0.5 / sg) / 0.75;
+        kp.es_beta = bpt * w;
+        kp.es_inv_hw = 2.0 / w;
+    } else if (kernel == MM_GAUSSIAN) {
+        kp.g_lambda = sg * msp / (sg - 0.5);   // step I.3 of the FGG algorithm
+        kp.g_t1 = kPi / kp.g_lambda;
+        kp.g_msp = msp;
+        for (int k = 0; k <= msp && k <= kMaxTaps / 2; ++k) kp.g_e3[k] = exp(-kp.g_t1 * k * k);
+    } else {
+        kp.kb_b = kPi * (2.0 - 1.0 / sg);      // b of Eq. Der:9
+        kp.kb_m = msp;
+        kp.kb_inv_norm = msp / sinh(kp.kb_b * msp);
+    }
+}
+
+// Oversampled grid: even, 2,3,5-smooth, >= sigma M and >= 2 w (the grid must be
+// longer than the spreading width), and splittable into two in-LDS sub-FFTs.
+static mm_status set_grid(Plan* p)
+{
+    uint64_t target = (uint64_t)ceil(p->sigma * p->M - 1e-9);
+    target = std::max<uint64_t>(target, 2ull * p->kp.w);
+    target = std::max<uint64_t>(target, 8ull);
+    uint64_t Mr = smooth_even_at_least(target);
+    int L1 = 0, L2 = 0;
+    while (true) {
+        if (Mr / 2 > (uint64_t)kMaxSub * kMaxSub) return MM_ERR_UNSUPPORTED;
+        if (split_len((int64_t)(Mr / 2), &L1, &L2)) break;
+        Mr = smooth_even_at_least(Mr + 2);
+    }
+    p->Mr = (int)Mr;
+    p->L = (int)(Mr / 2);
+    p->L1 = L1;
+    p->L2 = L2;
+    return MM_OK;
+}
+
+static int msp_for_width(int kernel, int w)
+{
+    if (kernel == MM_GAUSSIAN) return w / 2;
+    if (kernel == MM_KAISER_BESSEL) return (w - 1) / 2;
+    return (w + 1) / 2;
+}
+
 mm_status make_plan(int32_t N, mm_kernel kernel, double tol, mm_prec prec, const mm_tuning* tune, Plan* p)
 {
     memset(p, 0, sizeof(*p));
@@ -141,61 +318,50 @@ mm_status make_plan(int32_t N, mm_kernel kernel, double tol, mm_prec prec, const
         msp = (digits + 2) / 2 + 2;
         w = 2 * msp;                       // support +-M_sp cells
     }
-    if (tune && tune->width > 0) {
-        w = tune->width;
-        if (kernel == MM_GAUSSIAN) { if (w & 1) ++w; msp = w / 2; }
-        else if (kernel == MM_KAISER_BESSEL) { if (!(w & 1)) ++w; msp = (w - 1) / 2; }
-        else msp = (w + 1) / 2;
+    p->msp = msp;
+    const int req = tune ? tune->width : 0;
+    if (req > 0) {
+        w = req;
+        if (kernel == MM_GAUSSIAN && (w & 1)) ++w;
+        if (kernel == MM_KAISER_BESSEL && !(w & 1)) ++w;
+        msp = msp_for_width(kernel, w);
+    } else if (req == 0 && prec == MM_MIXED) {
+        // smallest width whose worst-case error estimate meets tol
+        const int step = (kernel == MM_ES) ? 1 : 2;
+        int wa = (kernel == MM_KAISER_BESSEL) ? 3 : 2;
+        bool found = false;
+        for (; wa <= kMaxTaps; wa += step) {
+            Plan q = *p;
+            int ma = msp_for_width(kernel, wa);
+            if (ma < 1) continue;
+            set_kernel(q.kp, kernel, wa, ma, sg, tune);
+            if (set_grid(&q) != MM_OK) continue;
+            if (estimate_error(q.kp, sg, q.Mr, N) <= tol) { found = true; break; }
+        }
+        if (found) { w = wa; msp = msp_for_width(kernel, w); }
     }
     if (w < 2 || w > kMaxTaps || msp < 1) return MM_ERR_ARG;
-    p->msp = msp;
-
-    KernParams& kp = p->kp;
-    kp.kind = kernel;
-    kp.w = w;
-    kp.hw = 0.5 * w;
-    if (kernel == MM_ES) {
-        double bpt = (tune && tune->es_beta_per_tap > 0) ? tune->es_beta_per_tap : 2.3;
-        kp.es_beta = bpt * w;              // beta = 2.3 omega, support +-omega/2 cells (Eq. Der:10-11)
-        kp.es_inv_hw = 2.0 / w;
-    } else if (kernel == MM_GAUSSIAN) {
-        kp.g_lambda = sg * msp / (sg - 0.5);   // step I.3 of the FGG algorithm
-        kp.g_t1 = kPi / kp.g_lambda;
-        kp.g_msp = msp;
-        for (int k = 0; k <= msp; ++k) kp.g_e3[k] = exp(-kp.g_t1 * k * k);
-    } else {
-        kp.kb_b = kPi * (2.0 - 1.0 / sg);      // b of Eq. Der:9
-        kp.kb_m = msp;
-        kp.kb_inv_norm = msp / sinh(kp.kb_b * msp);
+    p->wmsp = msp;
+    set_kernel(p->kp, kernel, w, msp, sg, tune);
+    mm_status gs = set_grid(p);
+    if (gs != MM_OK) return gs;
+    p->est_err = estimate_error(p->kp, sg, p->Mr, N);
+    {
+        const int q = (prec == MM_MIXED) ? 16 : 8;   // complex values per 128 bytes
+        p->L2p = (p->L2 + q - 1) / q * q;
     }
-
-    // Oversampled grid: even, 2,3,5-smooth, >= sigma M and >= 2 w (the grid
-    // must be longer than the spreading width).
-    uint64_t target = (uint64_t)ceil(sg * p->M - 1e-9);
-    target = std::max<uint64_t>(target, 2ull * w);
-    target = std::max<uint64_t>(target, 8ull);
-    uint64_t Mr = smooth_even_at_least(target);
-    int L1 = 0, L2 = 0;
-    while (true) {
-        if (Mr / 2 > (uint64_t)kMaxSub * kMaxSub) return MM_ERR_UNSUPPORTED;
-        if (split_len((int64_t)(Mr / 2), &L1, &L2)) break;
-        Mr = smooth_even_at_least(Mr + 2);
-    }
-    p->Mr = (int)Mr;
-    p->L = (int)(Mr / 2);
-    p->L1 = L1;
-    p->L2 = L2;
-    if (!make_fft_desc(L1, &p->F1) || !make_fft_desc(L2, &p->F2)) return MM_ERR_UNSUPPORTED;
+    if (!make_fft_desc(p->L1, &p->F1) || !make_fft_desc(p->L2, &p->F2)) return MM_ERR_UNSUPPORTED;
+    const int L1 = p->L1, L2 = p->L2;
 
     const size_t cs = (prec == MM_MIXED) ? 8 : 16;    // bytes per complex value
     const size_t budget = 64 * 1024;
     int CB = 16;
-    while (CB > 1 && (size_t)(CB * (L1 | 1) + L1) * cs > budget) CB >>= 1;
+    while (CB > 1 && (size_t)(CB * (L1 | 1) + L1) * cs + (size_t)((L1 + 3) & ~3) * 4 > budget) CB >>= 1;
     while (CB > 1 && CB / 2 >= L2) CB >>= 1;      // stays a power of two
     p->CB = CB;
     int R = 8;
     int P = L1 / 2 + 1;                          // row pairs (k1, L1 - k1), k1 = 0..L1/2
-    while (R > 1 && (size_t)(2 * R * (L2 | 1) + L2) * cs > budget) R >>= 1;
+    while (R > 1 && (size_t)(2 * R * (L2 | 1) + L2) * cs + (size_t)((L2 + 3) & ~3) * 4 > budget) R >>= 1;
     while (R > 1 && R / 2 >= P) R >>= 1;         // stays a power of two
     p->R = R;
     int tile = (prec == MM_MIXED) ? 2048 : 1024;
@@ -224,7 +390,7 @@ NufftWs nufft_workspace(const Plan& p, int32_t S)
     w.S_grid = (p.prec == MM_MIXED && !p.fused) ? S : (p.fused ? 0 : 1);
     const size_t tiles = (size_t)(p.Mr + p.tile - 1) / p.tile;
     w.ranges = o; o += al(8 * 6 * tiles * (size_t)w.S_grid);
-    w.grid = o; o += al(rs * (size_t)p.Mr * (size_t)w.S_grid);
+    w.grid = o; o += al(rs * 2 * (size_t)p.L1 * (size_t)p.L2p * (size_t)w.S_grid);
     w.total = o;
     return w;
 }

@@ -44,7 +44,8 @@ class Tuning(ctypes.Structure):
 class PlanInfo(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int32), ("width", ctypes.c_int32), ("msp", ctypes.c_int32), ("Mr", ctypes.c_int32),
                 ("L1", ctypes.c_int32), ("L2", ctypes.c_int32), ("fused", ctypes.c_int32), ("tile", ctypes.c_int32),
-                ("sigma", ctypes.c_double), ("beta", ctypes.c_double), ("tol", ctypes.c_double)]
+                ("sigma", ctypes.c_double), ("beta", ctypes.c_double), ("tol", ctypes.c_double),
+                ("est_err", ctypes.c_double)]
 
 
 _lib = None

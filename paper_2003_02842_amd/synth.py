@@ -284,9 +284,11 @@ def large_universe(D: int = 2000, n_lo: float = 1e4, n_hi: float = 1e6, N: int =
     (corr = normalise(B B^T + I)), variances U(0.05,0.3) daily, mu = 0.01.
     Event counts are log-uniform in [n_lo, n_hi]; given its count, an asset's
     event times are the order statistics of that many uniforms on [0, T_sec)
-    (a Poisson process conditioned on its count).  Factors are Brownian paths
-    on a ``factor_grid``-second grid observed by previous tick; idiosyncratic
-    increments are exact at each event.  Generated on ``device``."""
+    (a Poisson process conditioned on its count), drawn as normalised
+    cumulative sums of exponentials.  Factors are Brownian paths on a
+    ``factor_grid``-second grid observed by previous tick; idiosyncratic
+    increments are exact at each event.  All assets are drawn at once with flat
+    tensors on ``device``."""
     gc = _gen(seed, "cpu")
     g = _gen(seed + 1, device)
     B = 0.5 * torch.randn(D, n_factors, generator=gc, dtype=torch.float64)
@@ -296,30 +298,47 @@ def large_universe(D: int = 2000, n_lo: float = 1e4, n_hi: float = 1e6, N: int =
     counts = torch.round(torch.exp(logn)).to(torch.int64)          # observations per asset
     n_f = int(round(T_sec / factor_grid))
     hf = factor_grid / SECONDS_PER_DAY
-    F = torch.zeros(n_f + 1, n_factors, dtype=torch.float64, device=device)
-    F[1:] = torch.cumsum(math.sqrt(hf) * torch.randn(n_f, n_factors, generator=g, dtype=torch.float64,
-                                                    device=device), 0)
-    ev = counts - 1                                                   # returns per asset
-    offs = torch.zeros(D + 1, dtype=torch.int64)
-    offs[1:] = torch.cumsum(ev, 0)
-    E = int(offs[-1])
-    t = torch.empty(E, dtype=torch.float64, device=device)
-    dp = torch.empty(E, dtype=dp_dtype, device=device)
+    F = torch.zeros(n_factors, n_f + 1, dtype=torch.float64, device=device)
+    F[:, 1:] = torch.cumsum(math.sqrt(hf) * torch.randn(n_factors, n_f, generator=g, dtype=torch.float64,
+                                                       device=device), 1)
+    # observation times: asset i owns observations obs_off[i] .. obs_off[i+1]-1 and one
+    # extra exponential that normalises its cumulative sum
+    obs_off = torch.zeros(D + 1, dtype=torch.int64)
+    obs_off[1:] = torch.cumsum(counts, 0)
+    n_obs = int(obs_off[-1])
+    asset = torch.repeat_interleave(torch.arange(D, device=device), (counts + 1).to(device))
+    e = torch.empty(n_obs + D, dtype=torch.float64, device=device).exponential_(1.0, generator=g)
+    c = torch.cumsum(e, 0)
+    ext_off = (obs_off + torch.arange(D + 1)).to(device)            # offsets with the extra draw
+    base = torch.cat([torch.zeros(1, dtype=torch.float64, device=device), c[ext_off[1:-1] - 1]])
+    total = c[ext_off[1:] - 1] - base                               # per-asset normaliser
+    keep = torch.ones(n_obs + D, dtype=torch.bool, device=device)
+    keep[ext_off[1:] - 1] = False                                   # drop each asset's extra draw
+    a_obs = asset[keep]
+    tau = T_sec * ((c[keep] - base[a_obs]) / total[a_obs])
+    tau.clamp_(max=math.nextafter(T_sec, 0.0))
+    tday = tau / SECONDS_PER_DAY
+    # exact idiosyncratic Brownian motion at the observation times
+    first = torch.zeros(n_obs, dtype=torch.bool, device=device)
+    first[obs_off[:-1].to(device)] = True
+    dtd = torch.where(first, tday, tday - torch.roll(tday, 1))
+    z = torch.randn(n_obs, generator=g, dtype=torch.float64, device=device) * torch.sqrt(dtd)
+    cz = torch.cumsum(z, 0)
+    zbase = torch.cat([torch.zeros(1, dtype=torch.float64, device=device), cz[obs_off[1:-1].to(device) - 1]])
+    eps = cz - zbase[a_obs]
     Bd = (B / norm[:, None]).to(device)
-    for i in range(D):
-        n = int(counts[i])
-        e = torch.empty(n + 1, dtype=torch.float64, device=device).exponential_(1.0, generator=g)
-        c = torch.cumsum(e, 0)
-        tau = (T_sec * (c[:n] / c[n])).clamp_(max=math.nextafter(T_sec, 0.0))
-        tday = tau / SECONDS_PER_DAY
-        dtd = torch.diff(tday, prepend=torch.zeros(1, dtype=torch.float64, device=device))
-        eps = torch.cumsum(torch.sqrt(dtd) * torch.randn(n, generator=g, dtype=torch.float64, device=device), 0)
-        fidx = torch.clamp(torch.floor(tau / factor_grid).to(torch.int64), 0, n_f)
-        x = F[fidx] @ Bd[i] + eps / float(norm[i])
-        p = (0.01 - 0.5 * float(sig2[i])) * tday + math.sqrt(float(sig2[i])) * x
-        a, b = int(offs[i]), int(offs[i + 1])
-        t[a:b] = tau[:-1]
-        dp[a:b] = (p[1:] - p[:-1]).to(dp_dtype)
+    fidx = torch.clamp(torch.floor(tau / factor_grid).to(torch.int64), 0, n_f)
+    x = (F[:, fidx] * Bd[a_obs].T).sum(0) + eps / norm.to(device)[a_obs]
+    sd = torch.sqrt(sig2).to(device)[a_obs]
+    p = (0.01 - 0.5 * sig2.to(device)[a_obs]) * tday + sd * x
+    # returns attached to the left time; each asset's last observation carries none
+    last = torch.zeros(n_obs, dtype=torch.bool, device=device)
+    last[obs_off[1:].to(device) - 1] = True
+    ret = torch.roll(p, -1) - p
+    t = tau[~last].contiguous()
+    dp = ret[~last].to(dp_dtype).contiguous()
+    offs = torch.zeros(D + 1, dtype=torch.int64)
+    offs[1:] = torch.cumsum(counts - 1, 0)
     corr = (B @ B.T + torch.eye(D, dtype=torch.float64)) / torch.outer(norm, norm)
     return Workload("large-universe", offs.to(device), t, dp, 0.0, T_sec, 1, D, [N], seed,
                     dict(true_cov=cov_from(sig2, corr) * (T_sec / SECONDS_PER_DAY), counts=counts))

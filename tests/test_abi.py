@@ -120,3 +120,31 @@ def test_width_grows_as_tolerance_tightens():
     for kern in ("g", "kb", "es"):
         ws = [mm.plan_query(1000, kern, tol, "fp64")["width"] for tol in (1e-1, 1e-3, 1e-6, 1e-9, 1e-12, 1e-14)]
         assert ws == sorted(ws) and ws[0] < ws[-1]
+
+
+@pytest.mark.parametrize("kern", ["es", "kb", "g"])
+@pytest.mark.parametrize("tol", [1e-1, 1e-2, 1e-4, 1e-6])
+def test_mixed_default_width_meets_estimate(kern, tol):
+    """On the mixed path the planner takes the smallest width whose a-priori
+    error estimate is within tol; one tap less would not be."""
+    p = mm.plan_query(20_000, kern, tol, "mixed")
+    assert p["est_err"] <= tol
+    step = 1 if kern == "es" else 2
+    if p["width"] - step >= (3 if kern == "kb" else 2):
+        q = mm.plan_query(20_000, kern, tol, "mixed", {"width": p["width"] - step})
+        assert q["est_err"] > tol
+
+
+@pytest.mark.parametrize("kern", ["es", "kb", "g"])
+def test_error_estimate_decreases_with_width(kern):
+    step = 1 if kern == "es" else 2
+    w0 = 3 if kern == "kb" else 2
+    ests = [mm.plan_query(500, kern, 1e-6, "mixed", {"width": w})["est_err"] for w in range(w0, 17, step)]
+    assert all(b < a for a, b in zip(ests, ests[1:]))
+
+
+def test_fp64_default_is_paper_rule():
+    for kern, tol in (("es", 1e-12), ("kb", 1e-9), ("g", 1e-6)):
+        a = mm.plan_query(1000, kern, tol, "fp64")
+        b = mm.plan_query(1000, kern, tol, "mixed" if tol >= 1e-6 else "fp64", {"width": -1})
+        assert a["width"] == b["width"]
