@@ -21,6 +21,11 @@
 
 #include "mm_internal.h"
 
+// Events staged per LDS chunk by the FP32 spreading kernel (a multiple of 256).
+#ifndef MM_SPREAD_CHUNK
+#define MM_SPREAD_CHUNK 2048
+#endif
+
 namespace mm {
 
 template <typename T> struct CT;
@@ -306,12 +311,69 @@ __global__ void k_tile_ranges(const int64_t* __restrict__ offsets, const double*
     ranges[idx] = lo;
 }
 
+// One staged event.  key = first-tap cell relative to the tile plus w - 1 (a
+// small integer held exactly as a float); the tap at cell c has index
+// j = c + w - 1 - key and kernel argument x = j + x0 with x0 = 1 - f - hw.
+// a and b are per-event constants of the kernel in j:
+//   ES  a = x0/hw           z = j/hw + a, value exp(beta (sqrt(1 - z^2) - 1))
+//   G   a = -t1 x0^2,       exponent a + j (b - t1 j) = -t1 (j + x0)^2
+//       b = -2 t1 x0        (FP32 forms scale t1 by log2 e for exp2)
+//   KB  a = x0              x = j + a
+// The Gaussian needs both a and b (16-byte record); ES and KB only a (12 bytes),
+// which keeps more workgroups resident in LDS.
+template <typename T, bool HAS_B>
+struct EvRecT;
 template <typename T>
-struct EvRec {
-    int key;   // first-tap cell relative to the tile, plus w - 1 (>= 0)
-    T x0;      // kernel argument of the first tap, 1 - f - hw
-    T v;       // event strength
+struct EvRecT<T, true> {
+    T key, a, b, v;
 };
+template <typename T>
+struct EvRecT<T, false> {
+    T key, a, v;
+    static constexpr T b = (T)0;
+};
+template <typename T, int KIND>
+using EvRecK = EvRecT<T, KIND == MM_GAUSSIAN>;
+
+template <typename T, int KIND>
+__device__ __forceinline__ EvRecK<T, KIND> make_rec(int key, double x0, T v, const KernParams& kp)
+{
+    EvRecK<T, KIND> r;
+    r.key = (T)key;
+    r.v = v;
+    if constexpr (KIND == MM_ES) {
+        r.a = (T)(x0 * kp.es_inv_hw);
+    } else if constexpr (KIND == MM_GAUSSIAN) {
+        const double c = kp.g_t1 * ((sizeof(T) == 4) ? 1.4426950408889634074 : 1.0);
+        r.a = (T)(-c * x0 * x0);
+        r.b = (T)(-2.0 * c * x0);
+    } else {
+        r.a = (T)x0;
+    }
+    return r;
+}
+
+// v * kernel at tap index j (as a float) of a staged event.
+template <typename T, int KIND>
+__device__ __forceinline__ T pair_value(T j, const EvRecK<T, KIND>& r, const KEval<T>& k)
+{
+    if (KIND == MM_ES) {
+        const T z = fma(j, k.inv_hw, r.a);
+        if constexpr (sizeof(T) == 4) {
+            const float q = fmaxf(fmaf(-z, z, 1.0f), 0.0f);
+            return r.v * fexp2(fmaf(k.es_c, fsqrt(q), -k.es_c));
+        } else {
+            const double q = fmax(fma(-z, z, 1.0), 0.0);
+            return r.v * exp(fma(k.es_c, sqrt(q), -k.es_c));
+        }
+    } else if (KIND == MM_GAUSSIAN) {
+        const T e = fma(j, fma(j, -k.g_c, r.b), r.a);
+        if constexpr (sizeof(T) == 4) return r.v * fexp2(e);
+        else return r.v * exp(e);
+    } else {
+        return r.v * kern_eval<T, MM_KAISER_BESSEL>(j + r.a, k);
+    }
+}
 
 // Spreading (Eq. Der:15) by gathering: one workgroup per (series, tile of
 // 256*CPT cells); thread tid owns cells tid + 256 r.  The tile's events, sorted
@@ -326,9 +388,9 @@ __global__ __launch_bounds__(256) void k_spread(const double* __restrict__ t, co
 {
     constexpr bool EXACT = sizeof(T) == 8;
     constexpr int TC = 256 * CPT;
-    constexpr int EC = sizeof(T) == 4 ? 2048 : 1024;
+    constexpr int EC = sizeof(T) == 4 ? MM_SPREAD_CHUNK : 1024;
     constexpr int SB = EC / 256;   // events per thread per chunk
-    __shared__ EvRec<T> ev[EC];
+    __shared__ EvRecK<T, KIND> ev[EC];
     __shared__ unsigned short first[TC + kMaxTaps + 2];
     const int a = blockIdx.x * TC;
     const int len = min(TC, Mr - a);
@@ -377,11 +439,7 @@ __global__ __launch_bounds__(256) void k_spread(const double* __restrict__ t, co
                 int64_t l0;
                 double f;
                 cell_of<EXACT>(tv[u], t0, span, scale, Mr, kp.hw, l0, f);
-                EvRec<T> r;
-                r.key = (int)(l0 - shift) + w - 1;
-                r.x0 = (T)(1.0 - f - kp.hw);
-                r.v = (T)dv[u];
-                ev[i] = r;
+                ev[i] = make_rec<T, KIND>((int)(l0 - shift) + w - 1, 1.0 - f - kp.hw, (T)dv[u], kp);
             }
         }
         // prefetch the next chunk while this one is summed
@@ -395,10 +453,10 @@ __global__ __launch_bounds__(256) void k_spread(const double* __restrict__ t, co
             }
         }
         __syncthreads();
-        const int kmin = ev[0].key, kmax = ev[n - 1].key;
+        const int kmin = (int)ev[0].key, kmax = (int)ev[n - 1].key;
         for (int i = 1 + threadIdx.x; i < n; i += 256) {
-            const int k1 = ev[i].key;
-            for (int k = ev[i - 1].key + 1; k <= k1; ++k) first[k] = (unsigned short)i;
+            const int k1 = (int)ev[i].key;
+            for (int k = (int)ev[i - 1].key + 1; k <= k1; ++k) first[k] = (unsigned short)i;
         }
         __syncthreads();
 #pragma unroll
@@ -407,17 +465,17 @@ __global__ __launch_bounds__(256) void k_spread(const double* __restrict__ t, co
             if (c >= len || c + w - 1 < kmin || c > kmax) continue;
             const int lo = (c <= kmin) ? 0 : first[c];
             const int hi = (c + w > kmax) ? n : first[c + w];
-            const int cw = c + w - 1;
+            const T cw = (T)(c + w - 1);
             T s0 = (T)0, s1 = (T)0;
             int e = lo;
             for (; e + 1 < hi; e += 2) {
-                const EvRec<T> p = ev[e], q2 = ev[e + 1];
-                s0 += p.v * kern_eval<T, KIND>((T)(cw - p.key) + p.x0, ke);
-                s1 += q2.v * kern_eval<T, KIND>((T)(cw - q2.key) + q2.x0, ke);
+                const EvRecK<T, KIND> p0 = ev[e], p1 = ev[e + 1];
+                s0 += pair_value<T, KIND>(cw - p0.key, p0, ke);
+                s1 += pair_value<T, KIND>(cw - p1.key, p1, ke);
             }
             if (e < hi) {
-                const EvRec<T> p = ev[e];
-                s0 += p.v * kern_eval<T, KIND>((T)(cw - p.key) + p.x0, ke);
+                const EvRecK<T, KIND> p0 = ev[e];
+                s0 += pair_value<T, KIND>(cw - p0.key, p0, ke);
             }
             acc[r] += s0 + s1;
         }
