@@ -150,7 +150,8 @@ __global__ __launch_bounds__(256) void k_cov_fp64(int D, const double2* __restri
     for (int u = 0; u < 4; ++u)
         for (int v = 0; v < 4; ++v) {
             int i = bi * F64T + ty * 4 + u, j = bj * F64T + tx * 4 + v;
-            if (i < D && j < D) {
+            // i >= j only: (i, j) and (j, i) take one value, so Sigma is exactly symmetric
+            if (i < D && j <= i) {
                 cov[(int64_t)i * D + j] = acc[u][v];
                 cov[(int64_t)j * D + i] = acc[u][v];
             }
@@ -296,10 +297,19 @@ __global__ __launch_bounds__(256) void k_syrk_reduce(const float* __restrict__ p
         float acc = 0.f;
         for (int q = 0; q < nsplit; ++q) acc += P[q * tstride + li * ST + lj];
         const int i = bi * ST + li, j = bj * ST + lj;
+        if (bi == bj) {
+            // diagonal tile: (i, j) and (j, i) both come from the lower entry, so that
+            // Sigma is exactly symmetric (the MFMA sums the two in different orders)
+            if (i < D && j <= i) {
+                cov[(int64_t)i * D + j] = acc;
+                cov[(int64_t)j * D + i] = acc;
+            }
+            continue;
+        }
         if (i < D && j < D) cov[(int64_t)i * D + j] = acc;
         tileT[r][tx] = acc;
     }
-    if (bi == bj) return;   // a diagonal tile holds both (i, j) and (j, i) already
+    if (bi == bj) return;
     __syncthreads();
     for (int r = ty; r < 64; r += 4) {
         // row j = bj*ST + qj + r of Sigma, columns i = bi*ST + qi + tx
