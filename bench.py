@@ -53,6 +53,40 @@ def parse():
     return ap.parse_args()
 
 
+PROFILE_TRAFFIC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "hbm_traffic.large-universe.md")
+
+
+def source_hash() -> str:
+    """First 16 hex digits of the SHA-256 over the library's kernel sources."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    here = os.path.dirname(os.path.abspath(__file__))
+    for f in sorted(glob.glob(os.path.join(here, "paper_2003_02842_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary of the default workload, or None when that summary is
+    missing or was taken on other kernel sources."""
+    try:
+        with open(PROFILE_TRAFFIC) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    tag = "source_sha256_16: "
+    if tag not in text or text.split(tag, 1)[1].split()[0] != source_hash():
+        return None
+    for line in text.splitlines():
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if cells and cells[0] == kernel and len(cells) >= 7:
+            return float(cells[6])
+    return None
+
+
 def copy_calibration():
     import torch
     n = 1 << 30
@@ -125,6 +159,9 @@ def main():
 
     # roofline of the dominant kernel
     dom = max(kern, key=lambda k: kern[k]["avg_ms"])
+    default_workload = (a.D, a.n_lo, a.n_hi, a.N, a.kernel, a.tol, a.basis, a.seed, a.width) == \
+        (2000, 1e4, 1e6, 50_000, "es", 1e-6, "fejer", 20200310, 0)
+    traffic = measured_traffic(dom) if default_workload else None
     Mr = plan["Mr"]
     alg_bytes = {
         "k_spread": E * (8 + 4) + S * Mr * 4 + (S + 1) * 8,
@@ -136,12 +173,13 @@ def main():
         flops = 3.0 * D * (D + 1) * Kp
         ach = flops / (kern[dom]["avg_ms"] * 1e-3) / 1e12
         roof = {"kernel": dom, "bound": "mfma", "achieved": ach, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": ach / BF16_PEAK_TFLOPS, "traffic": None}
+                "frac": ach / BF16_PEAK_TFLOPS, "traffic": traffic}
     else:
         b = alg_bytes.get(dom)
         ach = b / (kern[dom]["avg_ms"] * 1e-3) / 1e9 if b else None
         roof = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": ach / HBM_PEAK_GBS if ach else None, "traffic": None}
+                "frac": ach / HBM_PEAK_GBS if ach else None, "traffic": traffic,
+                "alg_bytes": b}
     mfma_flops = 3.0 * D * (D + 1) * Kp
     mfma_t = kern.get("k_syrk_mfma", {}).get("avg_ms")
     contraction_roof = ({"kernel": "k_syrk_mfma", "bound": "mfma", "unit": "TFLOP/s", "peak": BF16_PEAK_TFLOPS,
@@ -176,24 +214,29 @@ def main():
         "roofline_contraction": contraction_roof,
     }
 
-    # plain FP64 GPU form on the same input, same tolerance, for the speed-up
+    # plain FP64 GPU form on the same input with the same kernel width (so the same
+    # accuracy), one launch chain per series and the FP64 contraction
     if not a.no_plain:
         dp64 = w.dp.to(torch.float64)
         coef64 = torch.empty((S, N + 1), dtype=torch.complex128, device=dev)
-        wsp = torch.empty(mm.nufft1_workspace_size(S, N, a.kernel, a.tol, "fp64"), dtype=torch.uint8, device=dev)
+        ptune = {"width": plan["width"]}
+        wsp = torch.empty(mm.nufft1_workspace_size(S, N, a.kernel, a.tol, "fp64", ptune), dtype=torch.uint8,
+                          device=dev)
 
-        def plain_step(tol):
-            mm.nufft1(w.offsets, w.t, dp64, w.t0, w.T, N, a.kernel, tol, "fp64", out=coef64, ws=wsp)
+        def plain_step():
+            mm.nufft1(w.offsets, w.t, dp64, w.t0, w.T, N, a.kernel, a.tol, "fp64", ptune, out=coef64, ws=wsp)
             return mm.cov(coef64, 1, D, [N], a.basis)
 
-        plain_step(a.tol)
+        plain_step()
         torch.cuda.synchronize()
         tp = time.perf_counter()
-        plain_step(a.tol)
+        ps, pr = plain_step()
         torch.cuda.synchronize()
         plain_ms = 1e3 * (time.perf_counter() - tp)
         out["plain_fp64_ms_per_step"] = plain_ms
+        out["plain_fp64_width"] = plan["width"]
         out["speedup_vs_plain_fp64"] = plain_ms / ms_step
+        del ps, pr
         # reference for the error: FP64 GPU form at tol 1e-12
         wsr = torch.empty(mm.nufft1_workspace_size(S, N, a.kernel, 1e-12, "fp64"), dtype=torch.uint8, device=dev)
         mm.nufft1(w.offsets, w.t, dp64, w.t0, w.T, N, a.kernel, 1e-12, "fp64", out=coef64, ws=wsr)
