@@ -146,6 +146,39 @@ mm_status mm_cov(int32_t G, int32_t D, const void* coef, int64_t ldc, const int3
                  mm_basis basis, mm_prec prec, void* cov, void* corr, void* ws, size_t ws_bytes,
                  void* stream);
 
+/* Bytes of device workspace mm_estimate needs for G*D series and the cutoffs Ns
+ * (host int32[nN]): room for the coefficients at k = 0..max(Ns), the NUFFT
+ * workspace and the contraction workspace. */
+mm_status mm_estimate_workspace_size(int32_t G, int32_t D, const int32_t* Ns, int32_t nN, mm_kernel kernel,
+                                     double tol, mm_prec prec, const mm_tuning* tune, size_t* bytes /* host */);
+
+/* Both stages in one call: the coefficients of all G*D series at N = max(Ns)
+ * (as mm_nufft1, without validation) and the estimates at every cutoff in Ns (as
+ * mm_cov).  One NUFFT serves every cutoff because c_k does not depend on N
+ * (Sec. 2.2, equation defining F(dp_i)(k)); Monte Carlo replicates are the G
+ * groups (Sec. 3).
+ *   coef     optional S x ldc output of the coefficients (ldc >= max(Ns)+1); NULL keeps
+ *            them in ws.
+ *   cov, corr  as mm_cov (corr may be NULL).
+ *   ws       device workspace of at least mm_estimate_workspace_size bytes (256-byte aligned).
+ *   use_graph 1: the first call with a given set of arguments (every pointer, size,
+ *            scalar, the stream and the current device) records the launch sequence
+ *            into a HIP graph and launches it; later calls with the same set launch
+ *            the recorded graph.  The graph reads the buffers at replay time, so new
+ *            data in the same buffers is picked up.  Requires a non-NULL stream (the
+ *            legacy default stream cannot be captured).  At most 64 graphs are kept;
+ *            recording a 65th synchronises the device and frees the oldest.
+ *            0: launched directly.
+ * Errors: MM_ERR_ARG, MM_ERR_TOL, MM_ERR_WORKSPACE, MM_ERR_UNSUPPORTED (G*D > 65535),
+ * MM_ERR_HIP. */
+mm_status mm_estimate(int32_t G, int32_t D, const int64_t* offsets, const double* t, const void* dp,
+                      int32_t dp_is_fp64, double t0, double T, const int32_t* Ns, int32_t nN, mm_basis basis,
+                      mm_kernel kernel, double tol, mm_prec prec, const mm_tuning* tune, void* coef, int64_t ldc,
+                      void* cov, void* corr, void* ws, size_t ws_bytes, int32_t use_graph, void* stream);
+
+/* Synchronises the device and frees every graph mm_estimate recorded. */
+mm_status mm_graph_cache_clear(void);
+
 /* Human-readable text of a status (static storage). */
 const char* mm_status_string(mm_status s);
 

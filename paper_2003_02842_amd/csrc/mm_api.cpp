@@ -39,25 +39,28 @@ hipEvent_t take_event()
 }
 }  // namespace
 
+// Set while this thread records a graph: event records are left out of captures.
+thread_local bool g_capturing = false;
+
 void prof_begin(const char* name, hipStream_t st)
 {
-    if (!g_prof_on) return;
+    if (!g_prof_on || g_capturing) return;
     std::lock_guard<std::mutex> lk(g_prof_mu);
     hipEvent_t e = take_event();
     if (!e) return;
-    hipEventRecord(e, st);
+    (void)hipEventRecord(e, st);
     g_prof_open[name] = e;
 }
 
 void prof_end(const char* name, hipStream_t st)
 {
-    if (!g_prof_on) return;
+    if (!g_prof_on || g_capturing) return;
     std::lock_guard<std::mutex> lk(g_prof_mu);
     auto it = g_prof_open.find(name);
     if (it == g_prof_open.end()) return;
     hipEvent_t e = take_event();
     if (!e) return;
-    hipEventRecord(e, st);
+    (void)hipEventRecord(e, st);
     g_prof_pending.push_back({name, it->second, e});
     g_prof_open.erase(it);
 }
@@ -66,8 +69,8 @@ static void prof_drain()
 {
     for (auto& r : g_prof_pending) {
         float ms = 0.f;
-        hipEventSynchronize(r.b);
-        hipEventElapsedTime(&ms, r.a, r.b);
+        (void)hipEventSynchronize(r.b);
+        (void)hipEventElapsedTime(&ms, r.a, r.b);
         auto& tot = g_prof_total[r.name];
         tot.first += ms;
         tot.second += 1;
@@ -82,6 +85,50 @@ static void prof_drain()
 using namespace mm;
 
 static mm_status hip_status(hipError_t e) { return e == hipSuccess ? MM_OK : MM_ERR_HIP; }
+
+// Tables, then the NUFFT of all S series (host checks already done).
+static hipError_t enqueue_nufft(const Plan& p, const NufftWs& w, char* wsb, int32_t S, const int64_t* offsets,
+                                const double* t, const void* dp, int32_t dp_is_fp64, double t0, double T,
+                                void* coef, int64_t ldc, hipStream_t st)
+{
+    hipError_t e = launch_prep(p, w, wsb, st);
+    if (e != hipSuccess) return e;
+    if (p.prec == MM_MIXED) {
+        if (p.fused) return launch_nufft_fused(p, w, wsb, S, offsets, t, dp, dp_is_fp64, t0, T, coef, ldc, st);
+        return launch_nufft_tiled(p, w, wsb, 0, S, offsets, t, dp, dp_is_fp64, t0, T, coef, ldc, st);
+    }
+    // plain form: one launch chain per series, grid buffer reused in stream order
+    for (int32_t sidx = 0; sidx < S && e == hipSuccess; ++sidx)
+        e = launch_nufft_tiled(p, w, wsb, sidx, 1, offsets, t, dp, dp_is_fp64, t0, T, coef, ldc, st);
+    return e;
+}
+
+static int small_d_limit(int32_t D) { return D * (D + 1) / 2 <= 1024; }
+
+// The contraction for every cutoff, then the correlation (host checks already done).
+static hipError_t enqueue_cov(int32_t G, int32_t D, const void* coef, int64_t ldc, const int32_t* Ns, int32_t nN,
+                              int32_t Nmax, mm_basis basis, mm_prec prec, void* cov, void* corr, char* ws,
+                              hipStream_t st)
+{
+    hipError_t e = hipSuccess;
+    const size_t es = prec == MM_MIXED ? 4 : 8;
+    if (small_d_limit(D)) {
+        Cutoffs cut;
+        cut.n = nN;
+        for (int q = 0; q < nN; ++q) cut.N[q] = Ns[q];
+        e = launch_cov_small(prec, G, D, coef, ldc, Nmax, cut, basis, cov, st);
+    } else {
+        for (int q = 0; q < nN && e == hipSuccess; ++q) {
+            char* cq = (char*)cov + (size_t)q * G * D * D * es;
+            if (prec == MM_MIXED)
+                e = launch_cov_mfma(G, D, coef, ldc, Ns[q], basis, cq, ws, st);
+            else
+                e = launch_cov_fp64(G, D, coef, ldc, Ns[q], basis, cq, st);
+        }
+    }
+    if (e == hipSuccess && corr) e = launch_corr(prec, (int64_t)nN * G, D, cov, corr, st);
+    return e;
+}
 
 extern "C" {
 
@@ -151,32 +198,18 @@ mm_status mm_nufft1(int32_t S, const int64_t* offsets, const double* t, const vo
     if (((uintptr_t)ws & 255) != 0) return MM_ERR_ARG;
     hipStream_t st = (hipStream_t)stream;
     char* wsb = (char*)ws;
-    hipError_t e = launch_prep(p, w, wsb, st);
-    if (e != hipSuccess) return MM_ERR_HIP;
     if (validate) {
         int* flag = (int*)(wsb + w.flag);
         if (hipMemsetAsync(flag, 0, sizeof(int), st) != hipSuccess) return MM_ERR_HIP;
-        e = launch_validate(S, offsets, t, dp, dp_is_fp64, t0, T, flag, st);
+        hipError_t e = launch_validate(S, offsets, t, dp, dp_is_fp64, t0, T, flag, st);
         if (e != hipSuccess) return MM_ERR_HIP;
         int host_flag = 0;
         if (hipMemcpyAsync(&host_flag, flag, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess) return MM_ERR_HIP;
         if (hipStreamSynchronize(st) != hipSuccess) return MM_ERR_HIP;
         if (host_flag) return MM_ERR_DATA;
     }
-    if (prec == MM_MIXED) {
-        if (p.fused)
-            e = launch_nufft_fused(p, w, wsb, S, offsets, t, dp, dp_is_fp64, t0, T, coef, ldc, st);
-        else
-            e = launch_nufft_tiled(p, w, wsb, 0, S, offsets, t, dp, dp_is_fp64, t0, T, coef, ldc, st);
-    } else {
-        // plain form: one launch chain per series, grid buffer reused in stream order
-        for (int32_t sidx = 0; sidx < S && e == hipSuccess; ++sidx)
-            e = launch_nufft_tiled(p, w, wsb, sidx, 1, offsets, t, dp, dp_is_fp64, t0, T, coef, ldc, st);
-    }
-    return hip_status(e);
+    return hip_status(enqueue_nufft(p, w, wsb, S, offsets, t, dp, dp_is_fp64, t0, T, coef, ldc, st));
 }
-
-static int small_d_limit(int32_t D) { return D * (D + 1) / 2 <= 1024; }
 
 mm_status mm_cov_workspace_size(int32_t G, int32_t D, int32_t Nmax, int32_t nN, mm_prec prec, size_t* bytes)
 {
@@ -193,35 +226,163 @@ mm_status mm_cov(int32_t G, int32_t D, const void* coef, int64_t ldc, const int3
     if (basis != MM_DIRICHLET && basis != MM_FEJER) return MM_ERR_ARG;
     if (prec != MM_PLAIN_FP64 && prec != MM_MIXED) return MM_ERR_ARG;
     if ((int64_t)G * D > 65535ll * 65535ll) return MM_ERR_UNSUPPORTED;
-    Cutoffs cut;
-    cut.n = nN;
     int32_t Nmax = 0;
     for (int q = 0; q < nN; ++q) {
         if (Ns[q] < 1 || (int64_t)Ns[q] > ldc - 1) return MM_ERR_ARG;
-        cut.N[q] = Ns[q];
         Nmax = std::max(Nmax, Ns[q]);
     }
     size_t need = 0;
     mm_cov_workspace_size(G, D, Nmax, nN, prec, &need);
     if (need > 0 && (!ws || ws_bytes < need)) return MM_ERR_WORKSPACE;
     if (need > 0 && ((uintptr_t)ws & 255) != 0) return MM_ERR_ARG;
-    hipStream_t st = (hipStream_t)stream;
-    hipError_t e = hipSuccess;
-    const size_t es = prec == MM_MIXED ? 4 : 8;
-    if (small_d_limit(D)) {
-        if (G > 65535) return MM_ERR_UNSUPPORTED;
-        e = launch_cov_small(prec, G, D, coef, ldc, Nmax, cut, basis, cov, st);
-    } else {
-        for (int q = 0; q < nN && e == hipSuccess; ++q) {
-            char* cq = (char*)cov + (size_t)q * G * D * D * es;
-            if (prec == MM_MIXED)
-                e = launch_cov_mfma(G, D, coef, ldc, Ns[q], basis, cq, (char*)ws, st);
-            else
-                e = launch_cov_fp64(G, D, coef, ldc, Ns[q], basis, cq, st);
-        }
+    if (small_d_limit(D) && G > 65535) return MM_ERR_UNSUPPORTED;
+    return hip_status(enqueue_cov(G, D, coef, ldc, Ns, nN, Nmax, basis, prec, cov, corr, (char*)ws,
+                                  (hipStream_t)stream));
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------------ both stages
+namespace {
+struct EstLayout {
+    size_t coef, nufft, cov, total;
+};
+
+size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+EstLayout est_layout(const Plan& p, int32_t S, int32_t G, int32_t D, int32_t Nmax, int32_t nN)
+{
+    EstLayout L;
+    const size_t cs = p.prec == MM_MIXED ? 8 : 16;
+    size_t cw = 0;
+    mm_cov_workspace_size(G, D, Nmax, nN, (mm_prec)p.prec, &cw);
+    L.coef = 0;
+    L.nufft = al256((size_t)S * (size_t)(Nmax + 1) * cs);
+    L.cov = L.nufft + al256(nufft_workspace(p, S).total);
+    L.total = L.cov + al256(cw);
+    return L;
+}
+
+// Graphs recorded by mm_estimate, keyed by the bytes of every argument.
+std::mutex g_graph_mu;
+std::map<std::string, hipGraphExec_t> g_graphs;
+std::vector<std::string> g_graph_order;
+constexpr size_t kMaxGraphs = 64;
+
+template <typename V>
+void put(std::string& k, const V& v)
+{
+    k.append(reinterpret_cast<const char*>(&v), sizeof(v));
+}
+}  // namespace
+
+extern "C" {
+
+mm_status mm_estimate_workspace_size(int32_t G, int32_t D, const int32_t* Ns, int32_t nN, mm_kernel kernel,
+                                     double tol, mm_prec prec, const mm_tuning* tune, size_t* bytes)
+{
+    if (!bytes || !Ns || G < 1 || D < 1 || nN < 1 || nN > kMaxCutoffs) return MM_ERR_ARG;
+    int32_t Nmax = 0;
+    for (int q = 0; q < nN; ++q) {
+        if (Ns[q] < 1) return MM_ERR_ARG;
+        Nmax = std::max(Nmax, Ns[q]);
     }
-    if (e == hipSuccess && corr) e = launch_corr(prec, (int64_t)nN * G, D, cov, corr, st);
-    return hip_status(e);
+    if ((int64_t)G * D > 65535) return MM_ERR_UNSUPPORTED;
+    Plan p;
+    mm_status s = make_plan(Nmax, kernel, tol, prec, tune, &p);
+    if (s != MM_OK) return s;
+    *bytes = est_layout(p, G * D, G, D, Nmax, nN).total;
+    return MM_OK;
+}
+
+mm_status mm_estimate(int32_t G, int32_t D, const int64_t* offsets, const double* t, const void* dp,
+                      int32_t dp_is_fp64, double t0, double T, const int32_t* Ns, int32_t nN, mm_basis basis,
+                      mm_kernel kernel, double tol, mm_prec prec, const mm_tuning* tune, void* coef, int64_t ldc,
+                      void* cov, void* corr, void* ws, size_t ws_bytes, int32_t use_graph, void* stream)
+{
+    if (G < 1 || D < 1 || !offsets || !t || !dp || !cov || !Ns || nN < 1 || nN > kMaxCutoffs) return MM_ERR_ARG;
+    if ((dp_is_fp64 != 0 && dp_is_fp64 != 1) || (use_graph != 0 && use_graph != 1)) return MM_ERR_ARG;
+    if (!isfinite(t0) || !isfinite(T) || !(T > t0)) return MM_ERR_ARG;
+    if (basis != MM_DIRICHLET && basis != MM_FEJER) return MM_ERR_ARG;
+    if (use_graph && !stream) return MM_ERR_ARG;   // the legacy default stream cannot be captured
+    if ((int64_t)G * D > 65535) return MM_ERR_UNSUPPORTED;
+    int32_t Nmax = 0;
+    for (int q = 0; q < nN; ++q) {
+        if (Ns[q] < 1) return MM_ERR_ARG;
+        Nmax = std::max(Nmax, Ns[q]);
+    }
+    if (coef && ldc < (int64_t)Nmax + 1) return MM_ERR_ARG;
+    Plan p;
+    mm_status s = make_plan(Nmax, kernel, tol, prec, tune, &p);
+    if (s != MM_OK) return s;
+    const int32_t S = G * D;
+    const EstLayout L = est_layout(p, S, G, D, Nmax, nN);
+    if (!ws || ws_bytes < L.total) return MM_ERR_WORKSPACE;
+    if (((uintptr_t)ws & 255) != 0) return MM_ERR_ARG;
+    char* wsb = (char*)ws;
+    if (!coef) {
+        coef = wsb + L.coef;
+        ldc = (int64_t)Nmax + 1;
+    }
+    const NufftWs w = nufft_workspace(p, S);
+    hipStream_t st = (hipStream_t)stream;
+    auto enqueue = [&]() -> hipError_t {
+        hipError_t e = enqueue_nufft(p, w, wsb + L.nufft, S, offsets, t, dp, dp_is_fp64, t0, T, coef, ldc, st);
+        if (e != hipSuccess) return e;
+        return enqueue_cov(G, D, coef, ldc, Ns, nN, Nmax, basis, prec, cov, corr, wsb + L.cov, st);
+    };
+    if (!use_graph) return hip_status(enqueue());
+
+    std::string key;
+    const void* ptrs[] = {offsets, t, dp, coef, cov, corr, ws, stream};
+    put(key, G); put(key, D); put(key, dp_is_fp64); put(key, t0); put(key, T); put(key, nN);
+    key.append(reinterpret_cast<const char*>(Ns), sizeof(int32_t) * (size_t)nN);
+    put(key, basis); put(key, kernel); put(key, tol); put(key, prec); put(key, ldc); put(key, ws_bytes);
+    put(key, ptrs);
+    const mm_tuning tz = tune ? *tune : mm_tuning{0, 0.0, 0, 0, 0.0};
+    put(key, tz.width); put(key, tz.sigma); put(key, tz.tile); put(key, tz.fused); put(key, tz.es_beta_per_tap);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return MM_ERR_HIP;
+    put(key, dev);
+
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    auto it = g_graphs.find(key);
+    if (it == g_graphs.end()) {
+        hipGraph_t graph = nullptr;
+        if (hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed) != hipSuccess) return MM_ERR_HIP;
+        g_capturing = true;
+        hipError_t e = enqueue();
+        g_capturing = false;
+        hipError_t ec = hipStreamEndCapture(st, &graph);
+        if (e != hipSuccess || ec != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return MM_ERR_HIP;
+        }
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return MM_ERR_HIP;
+        if (g_graphs.size() >= kMaxGraphs) {
+            // the oldest graph may still run on its stream: wait for the device before freeing it
+            if (hipDeviceSynchronize() != hipSuccess) return MM_ERR_HIP;
+            (void)hipGraphExecDestroy(g_graphs[g_graph_order.front()]);
+            g_graphs.erase(g_graph_order.front());
+            g_graph_order.erase(g_graph_order.begin());
+        }
+        it = g_graphs.emplace(key, exec).first;
+        g_graph_order.push_back(key);
+    }
+    return hip_status(hipGraphLaunch(it->second, st));
+}
+
+mm_status mm_graph_cache_clear(void)
+{
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    if (!g_graphs.empty() && hipDeviceSynchronize() != hipSuccess) return MM_ERR_HIP;
+    for (auto& kv : g_graphs) (void)hipGraphExecDestroy(kv.second);
+    g_graphs.clear();
+    g_graph_order.clear();
+    return MM_OK;
 }
 
 mm_status mm_profile_enable(int32_t on)

@@ -27,6 +27,7 @@ _BASES = {"dirichlet": DIRICHLET, "fejer": FEJER}
 _PRECS = {"fp64": PLAIN_FP64, "plain": PLAIN_FP64, "mixed": MIXED}
 
 EXPORTED = ["mm_plan_query", "mm_nufft1_workspace_size", "mm_nufft1", "mm_cov_workspace_size", "mm_cov",
+            "mm_estimate_workspace_size", "mm_estimate", "mm_graph_cache_clear",
             "mm_status_string", "mm_profile_enable", "mm_profile_read", "mm_profile_reset"]
 
 
@@ -64,6 +65,10 @@ def lib():
         L.mm_nufft1.argtypes = [i32, P, P, P, i32, f64, f64, i32, i32, f64, i32, P, P, i64, P, sz, i32, P]
         L.mm_cov_workspace_size.argtypes = [i32, i32, i32, i32, i32, ctypes.POINTER(sz)]
         L.mm_cov.argtypes = [i32, i32, P, i64, P, i32, i32, i32, P, P, P, sz, P]
+        L.mm_estimate_workspace_size.argtypes = [i32, i32, P, i32, i32, f64, i32, P, ctypes.POINTER(sz)]
+        L.mm_estimate.argtypes = [i32, i32, P, P, P, i32, f64, f64, P, i32, i32, i32, f64, i32, P, P, i64, P, P, P,
+                                  sz, i32, P]
+        L.mm_graph_cache_clear.argtypes = []
         L.mm_status_string.argtypes = [i32]
         L.mm_status_string.restype = ctypes.c_char_p
         L.mm_profile_enable.argtypes = [i32]
@@ -199,12 +204,72 @@ def cov(coef: torch.Tensor, G: int, D: int, Ns, basis="dirichlet", correlation: 
     return covt, corrt
 
 
-def estimate(w, Ns=None, basis="dirichlet", kernel="es", tol: float = 1e-12, prec="fp64", tune=None):
-    """Both stages for a ``synth.Workload`` already on the device."""
-    Ns = list(w.Ns if Ns is None else Ns)
-    coef = nufft1(w.offsets, w.t, w.dp, w.t0, w.T, max(Ns), kernel, tol, prec, tune)
-    S, R = cov(coef, w.G, w.D, Ns, basis)
-    return coef, S, R
+def estimate_workspace_size(G: int, D: int, Ns, kernel="es", tol: float = 1e-12, prec="fp64", tune=None) -> int:
+    Ns = [int(n) for n in Ns]
+    arr = (ctypes.c_int32 * len(Ns))(*Ns)
+    out = ctypes.c_size_t(0)
+    t = _tuning(tune)
+    _check(lib().mm_estimate_workspace_size(int(G), int(D), arr, len(Ns), _enum(kernel, _KERNELS, "kernel"),
+                                            float(tol), _enum(prec, _PRECS, "precision"),
+                                            ctypes.byref(t) if t is not None else None, ctypes.byref(out)),
+           "mm_estimate_workspace_size")
+    return int(out.value)
+
+
+_graph_streams = {}
+
+
+def estimate(offsets: torch.Tensor, t: torch.Tensor, dp: torch.Tensor, t0: float, T: float, G: int, D: int, Ns,
+             basis="dirichlet", kernel="es", tol: float = 1e-12, prec="fp64", tune=None, use_graph: bool = False,
+             coef: torch.Tensor = None, correlation: bool = True, ws: torch.Tensor = None,
+             out=None):
+    """Both stages in one library call (mm_estimate): Sigma (and R) of shape
+    (len(Ns), G, D, D) for G groups of D consecutive CSR series.  With
+    ``use_graph`` the launch sequence is recorded once into a HIP graph and
+    replayed by later calls with the same tensors; on torch's default stream the
+    call runs on a side stream ordered after and before the current one.
+    ``out`` = (cov, corr) reuses output tensors (needed for replays to hit the
+    same graph)."""
+    p = _enum(prec, _PRECS, "precision")
+    if not (offsets.is_cuda and t.is_cuda and dp.is_cuda):
+        raise ValueError("offsets, t and dp must be device tensors")
+    if offsets.dtype != torch.int64 or t.dtype != torch.float64 or dp.dtype not in (torch.float32, torch.float64):
+        raise TypeError("offsets int64, t float64, dp float32/float64 expected")
+    if not (offsets.is_contiguous() and t.is_contiguous() and dp.is_contiguous()):
+        raise ValueError("offsets, t and dp must be contiguous")
+    Ns = [int(n) for n in Ns]
+    arr = (ctypes.c_int32 * len(Ns))(*Ns)
+    rdt = torch.float32 if p == MIXED else torch.float64
+    if out is None:
+        covt = torch.empty((len(Ns), G, D, D), dtype=rdt, device=t.device)
+        corrt = torch.empty_like(covt) if correlation else None
+    else:
+        covt, corrt = out
+    need = estimate_workspace_size(G, D, Ns, kernel, tol, prec, tune)
+    if ws is None or ws.numel() < need:
+        ws = _workspace(need, t.device)
+    tt = _tuning(tune)
+    ldc = coef.stride(0) if coef is not None else 0
+    args = [int(G), int(D), _ptr(offsets), _ptr(t), _ptr(dp), int(dp.dtype == torch.float64), float(t0), float(T),
+            arr, len(Ns), _enum(basis, _BASES, "basis"), _enum(kernel, _KERNELS, "kernel"), float(tol), p,
+            ctypes.byref(tt) if tt is not None else None, _ptr(coef), ldc, _ptr(covt), _ptr(corrt), _ptr(ws),
+            ws.numel(), int(bool(use_graph))]
+    cur = torch.cuda.current_stream()
+    if use_graph and cur.cuda_stream == 0:
+        side = _graph_streams.get(t.device)
+        if side is None:
+            side = _graph_streams[t.device] = torch.cuda.Stream(device=t.device)
+        side.wait_stream(cur)
+        st = lib().mm_estimate(*args, ctypes.c_void_p(side.cuda_stream))
+        cur.wait_stream(side)
+    else:
+        st = lib().mm_estimate(*args, ctypes.c_void_p(cur.cuda_stream))
+    _check(st, "mm_estimate")
+    return covt, corrt, ws
+
+
+def graph_cache_clear():
+    _check(lib().mm_graph_cache_clear(), "mm_graph_cache_clear")
 
 
 def profile_enable(on: bool = True):

@@ -148,3 +148,37 @@ def test_fp64_default_is_paper_rule():
         a = mm.plan_query(1000, kern, tol, "fp64")
         b = mm.plan_query(1000, kern, tol, "mixed" if tol >= 1e-6 else "fp64", {"width": -1})
         assert a["width"] == b["width"]
+
+
+def _est_raw(**kw):
+    a = dict(G=2, D=3, offsets=1, t=1, dp=1, dpf=0, t0=0.0, T=1.0, Ns=[5, 9], basis=1, kernel=2, tol=1e-6, prec=1,
+             tune=None, coef=0, ldc=0, cov=1, corr=0, ws=256, wsb=1 << 40, graph=0, stream=None)
+    a.update(kw)
+    P = ctypes.c_void_p
+    arr = (ctypes.c_int32 * max(1, len(a["Ns"])))(*a["Ns"]) if a["Ns"] is not None else None
+    n = a.get("nN", len(a["Ns"]) if a["Ns"] is not None else 1)
+    return mm.lib().mm_estimate(a["G"], a["D"], P(a["offsets"]), P(a["t"]), P(a["dp"]), a["dpf"], a["t0"], a["T"],
+                                arr, n, a["basis"], a["kernel"], a["tol"], a["prec"], a["tune"], P(a["coef"]),
+                                a["ldc"], P(a["cov"]), P(a["corr"]), P(a["ws"]), a["wsb"], a["graph"],
+                                P(a["stream"]) if a["stream"] else None)
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(G=0), mm.MM_ERR_ARG), (dict(D=0), mm.MM_ERR_ARG), (dict(t=0), mm.MM_ERR_ARG), (dict(cov=0), mm.MM_ERR_ARG),
+    (dict(Ns=None), mm.MM_ERR_ARG), (dict(Ns=[0]), mm.MM_ERR_ARG), (dict(nN=0), mm.MM_ERR_ARG),
+    (dict(basis=5), mm.MM_ERR_ARG), (dict(dpf=3), mm.MM_ERR_ARG), (dict(graph=2), mm.MM_ERR_ARG),
+    (dict(graph=1), mm.MM_ERR_ARG),                      # graphs need a non-default stream
+    (dict(T=-1.0), mm.MM_ERR_ARG), (dict(coef=1, ldc=5), mm.MM_ERR_ARG), (dict(tol=1e-9), mm.MM_ERR_TOL),
+    (dict(G=300, D=300), mm.MM_ERR_UNSUPPORTED), (dict(wsb=1024), mm.MM_ERR_WORKSPACE), (dict(ws=0), mm.MM_ERR_WORKSPACE),
+    (dict(ws=300), mm.MM_ERR_ARG),
+])
+def test_estimate_rejects_before_launch(kw, status):
+    assert _est_raw(**kw) == status
+
+
+def test_estimate_workspace_covers_both_stages():
+    G, D, Ns = 4, 10, [1, 7, 2000]
+    est = mm.estimate_workspace_size(G, D, Ns, "es", 1e-6, "mixed")
+    nufft = mm.nufft1_workspace_size(G * D, max(Ns), "es", 1e-6, "mixed")
+    coef = G * D * (max(Ns) + 1) * 8
+    assert est >= nufft + coef + mm.cov_workspace_size(G, D, max(Ns), len(Ns), "mixed")
