@@ -72,6 +72,8 @@ typedef struct {
     int32_t tile;              /* cells per spreading tile (tiled path) */
     int32_t fused;             /* -1: never use the LDS-resident fused path, 0: auto, 1: prefer it */
     double es_beta_per_tap;    /* ES shape: beta = es_beta_per_tap * width (paper: 2.3) */
+    int32_t fft_generic;       /* 1: run the grid FFT with the generic in-LDS radix passes even where both
+                                  sub-lengths split into register codelets (0: auto) */
 } mm_tuning;
 
 /* What the planner chose (host only, no device work). */

@@ -1,0 +1,500 @@
+// Grid FFT of the type-1 NUFFT (Eq. Der:16) with one LDS exchange per pass.
+//
+// The packed complex grid z_j = x_2j + i x_2j+1 (length L = Mr/2 = L1 L2) is an
+// L1 x L2 row-major matrix (rows L2p apart).  Both passes split their
+// sub-transform of length n = A B by Cooley-Tukey, with n = B n_a + n_b and
+// k = k_a + A k_b:
+//   X[k_a + A k_b] = sum_{n_b} W_B^{n_b k_b} W_n^{n_b k_a} sum_{n_a} x[B n_a + n_b] W_A^{n_a k_a}
+// Step A (size-A DFTs) runs on values a thread loads straight from HBM, the
+// product with W_n^{n_b k_a} follows, one LDS exchange regroups the values, and
+// step B (size-B DFTs) leaves every output in natural order.  Both DFT sizes are
+// 2,3,5-smooth and at most 32; each is a fully unrolled register codelet with
+// compile-time twiddles.
+//
+//   k_fft_cols_ab  length-L1 transforms of the columns, times the four-step
+//                  twiddle W_L^{k1 l2}, in place
+//   k_fft_rows_ab  length-L2 transforms of the row pairs (k1, L1 - k1), the
+//                  real-input untangling, deconvolution (Eq. Der:17) and the 1/2pi
+//                  of the coefficient definition; writes c_k, k = 0..N
+//
+// Long twiddle tables are split in two, W^m = lo[m mod LO] hi[m / LO], so both
+// halves (about 2 sqrt(L) entries) sit in LDS.
+#include <hip/hip_runtime.h>
+
+#include "mm_internal.h"
+
+namespace mm {
+
+template <typename T> struct CTf;
+template <> struct CTf<float> { using type = float2; };
+template <> struct CTf<double> { using type = double2; };
+
+// ---------------------------------------------------------------- compile-time twiddles
+// cos and sin of 2 pi m / n by octant reduction and Taylor series (|x| <= pi/4).
+__host__ __device__ constexpr double cx_sin_t(double x)
+{
+    double x2 = x * x, term = x, sum = x;
+    for (int k = 1; k < 14; ++k) {
+        term *= -x2 / ((2.0 * k) * (2.0 * k + 1.0));
+        sum += term;
+    }
+    return sum;
+}
+__host__ __device__ constexpr double cx_cos_t(double x)
+{
+    double x2 = x * x, term = 1.0, sum = 1.0;
+    for (int k = 1; k < 14; ++k) {
+        term *= -x2 / ((2.0 * k - 1.0) * (2.0 * k));
+        sum += term;
+    }
+    return sum;
+}
+// cos(2 pi f) for f in [0, 1/4]
+__host__ __device__ constexpr double cx_cos_q(double f)
+{
+    constexpr double pi = 3.141592653589793238462643383279502884;
+    return f <= 0.125 ? cx_cos_t(2.0 * pi * f) : cx_sin_t(2.0 * pi * (0.25 - f));
+}
+__host__ __device__ constexpr double cx_cos2pi(int m, int n)
+{
+    m %= n;
+    if (m < 0) m += n;
+    double f = (double)m / (double)n;
+    if (f > 0.5) f = 1.0 - f;                       // cos even about 1/2
+    return f > 0.25 ? -cx_cos_q(0.5 - f) : cx_cos_q(f);
+}
+__host__ __device__ constexpr double cx_sin2pi(int m, int n)
+{
+    // sin(2 pi m/n) = cos(2 pi (m/n - 1/4)) = cos(2 pi (4m - n) / 4n)
+    return cx_cos2pi(4 * (m % n) - n, 4 * n);
+}
+
+// cos and sin of 2 pi m / N, m < N, evaluated by the compiler.
+template <int N>
+struct TwTable {
+    double c[N], s[N];
+    constexpr TwTable() : c(), s()
+    {
+        for (int m = 0; m < N; ++m) {
+            c[m] = cx_cos2pi(m, N);
+            s[m] = cx_sin2pi(m, N);
+        }
+    }
+};
+template <int N>
+struct TwConst {
+    static constexpr TwTable<N> tab{};
+};
+
+// v * W_N^m = v exp(-2 pi i m / N); m is a constant once the codelet loops unroll.
+template <typename T, int N>
+__device__ __forceinline__ typename CTf<T>::type twc(typename CTf<T>::type v, int m)
+{
+    using C = typename CTf<T>::type;
+    m %= N;
+    if (m == 0) return v;
+    if (4 * m == N) return C{v.y, -v.x};
+    if (2 * m == N) return C{-v.x, -v.y};
+    if (4 * m == 3 * N) return C{-v.y, v.x};
+    const T c = (T)TwConst<N>::tab.c[m], s = (T)TwConst<N>::tab.s[m];
+    return C{fma(v.x, c, v.y * s), fma(v.y, c, -(v.x * s))};
+}
+
+// ---------------------------------------------------------------- register codelets
+// In-place forward DFT of R <= 5 values, exp(-2 pi i/R).
+template <typename T, int R>
+__device__ __forceinline__ void dft_small(typename CTf<T>::type* v)
+{
+    using C = typename CTf<T>::type;
+    if constexpr (R == 2) {
+        C a = v[0], b = v[1];
+        v[0] = C{a.x + b.x, a.y + b.y};
+        v[1] = C{a.x - b.x, a.y - b.y};
+    } else if constexpr (R == 3) {
+        const T s3 = (T)0.86602540378443864676;
+        C t1 = C{v[1].x + v[2].x, v[1].y + v[2].y};
+        C t2 = C{v[0].x - (T)0.5 * t1.x, v[0].y - (T)0.5 * t1.y};
+        C t3 = C{s3 * (v[1].x - v[2].x), s3 * (v[1].y - v[2].y)};
+        v[0] = C{v[0].x + t1.x, v[0].y + t1.y};
+        v[1] = C{t2.x + t3.y, t2.y - t3.x};
+        v[2] = C{t2.x - t3.y, t2.y + t3.x};
+    } else if constexpr (R == 4) {
+        C a = C{v[0].x + v[2].x, v[0].y + v[2].y}, b = C{v[0].x - v[2].x, v[0].y - v[2].y};
+        C c = C{v[1].x + v[3].x, v[1].y + v[3].y}, d = C{v[1].x - v[3].x, v[1].y - v[3].y};
+        v[0] = C{a.x + c.x, a.y + c.y};
+        v[2] = C{a.x - c.x, a.y - c.y};
+        v[1] = C{b.x + d.y, b.y - d.x};
+        v[3] = C{b.x - d.y, b.y + d.x};
+    } else if constexpr (R == 5) {
+        const T c1 = (T)0.30901699437494742410, c2 = (T)-0.80901699437494742410;
+        const T s1 = (T)0.95105651629515357212, s2 = (T)0.58778525229247312917;
+        C x0 = v[0];
+        C a1 = C{v[1].x + v[4].x, v[1].y + v[4].y}, b1 = C{v[1].x - v[4].x, v[1].y - v[4].y};
+        C a2 = C{v[2].x + v[3].x, v[2].y + v[3].y}, b2 = C{v[2].x - v[3].x, v[2].y - v[3].y};
+        C p1 = C{x0.x + c1 * a1.x + c2 * a2.x, x0.y + c1 * a1.y + c2 * a2.y};
+        C q1 = C{s1 * b1.x + s2 * b2.x, s1 * b1.y + s2 * b2.y};
+        C p2 = C{x0.x + c2 * a1.x + c1 * a2.x, x0.y + c2 * a1.y + c1 * a2.y};
+        C q2 = C{s2 * b1.x - s1 * b2.x, s2 * b1.y - s1 * b2.y};
+        v[0] = C{x0.x + a1.x + a2.x, x0.y + a1.y + a2.y};
+        v[1] = C{p1.x + q1.y, p1.y - q1.x};
+        v[4] = C{p1.x - q1.y, p1.y + q1.x};
+        v[2] = C{p2.x + q2.y, p2.y - q2.x};
+        v[3] = C{p2.x - q2.y, p2.y + q2.x};
+    }
+}
+
+// In-place forward DFT of N values (2,3,5-smooth), natural order in and out:
+// N = P Q, n = Q n_p + n_q, k = k_p + P k_q.
+template <typename T, int N>
+__device__ __forceinline__ void dft_reg(typename CTf<T>::type* x)
+{
+    using C = typename CTf<T>::type;
+    if constexpr (N <= 1) {
+        return;
+    } else if constexpr (N <= 5) {
+        dft_small<T, N>(x);
+    } else {
+        constexpr int P = (N % 4 == 0 && N != 8) ? 4 : (N % 5 == 0 ? 5 : (N % 3 == 0 ? 3 : (N % 4 == 0 ? 4 : 2)));
+        constexpr int Q = N / P;
+        C t[N];
+#pragma unroll
+        for (int nq = 0; nq < Q; ++nq) {
+            C v[P];
+#pragma unroll
+            for (int np = 0; np < P; ++np) v[np] = x[Q * np + nq];
+            dft_small<T, P>(v);
+#pragma unroll
+            for (int kp = 0; kp < P; ++kp) t[nq * P + kp] = twc<T, N>(v[kp], nq * kp);
+        }
+#pragma unroll
+        for (int kp = 0; kp < P; ++kp) {
+            C u[Q];
+#pragma unroll
+            for (int nq = 0; nq < Q; ++nq) u[nq] = t[nq * P + kp];
+            dft_reg<T, Q>(u);
+#pragma unroll
+            for (int kq = 0; kq < Q; ++kq) x[kp + P * kq] = u[kq];
+        }
+    }
+}
+
+template <typename C>
+__device__ __forceinline__ C cmulf(C a, C b)
+{
+    return C{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+
+// W^m from the split table: lo[m & (LO-1)] * hi[m >> lo_bits].
+template <typename C>
+__device__ __forceinline__ C tw_split(const C* lo, const C* hi, int m, int lo_bits)
+{
+    return cmulf(lo[m & ((1 << lo_bits) - 1)], hi[m >> lo_bits]);
+}
+
+// ---------------------------------------------------------------- column pass
+// Step A of one column: values n = B n_a + nb (n_a < A) straight from the grid,
+// size-A DFT, times W_L1^{nb k_a}, into LDS block k_a.
+template <typename T, int A>
+__device__ __forceinline__ void col_step_a(const typename CTf<T>::type* z, int L2p, int B, int nb, int col,
+                                           const typename CTf<T>::type* tw1, typename CTf<T>::type* sh, int blk,
+                                           int slot)
+{
+    using C = typename CTf<T>::type;
+    C x[A];
+#pragma unroll
+    for (int a = 0; a < A; ++a) x[a] = z[(int64_t)(B * a + nb) * L2p + col];
+    dft_reg<T, A>(x);
+#pragma unroll
+    for (int a = 0; a < A; ++a) sh[a * blk + slot] = a ? cmulf(x[a], tw1[nb * a]) : x[a];
+}
+
+// Step B of one column: LDS block ka, size-B DFT, outputs k1 = ka + A k_b times
+// the four-step twiddle W_L^{k1 col}, back to the grid.
+template <typename T, int B>
+__device__ __forceinline__ void col_step_b(typename CTf<T>::type* z, int L2p, int A, int ka, int col, int C_,
+                                           const typename CTf<T>::type* sh, int blk, int c,
+                                           const typename CTf<T>::type* lo, const typename CTf<T>::type* hi,
+                                           int lo_bits)
+{
+    using C = typename CTf<T>::type;
+    C y[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) y[b] = sh[ka * blk + b * C_ + c];
+    dft_reg<T, B>(y);
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const int k1 = ka + A * b;
+        z[(int64_t)k1 * L2p + col] = cmulf(y[b], tw_split(lo, hi, k1 * col, lo_bits));
+    }
+}
+
+#define MM_CODELETS(X) X(1) X(2) X(3) X(4) X(5) X(6) X(8) X(9) X(10) X(12) X(15) X(16) X(18) X(20) X(24) \
+    X(25) X(27) X(30) X(32)
+
+// Workgroup (column block, series): CC consecutive columns, each transformed by
+// B threads in step A and A threads in step B.  LDS: tw1 (L1), the split W_L
+// table, then A blocks of B*CC values (one pad value per block).
+template <typename T>
+__global__ __launch_bounds__(512) void k_fft_cols_ab(T* __restrict__ grid, int64_t grid_stride, int L1, int L2,
+                                                     int L2p, int A, int B, int CC,
+                                                     const typename CTf<T>::type* __restrict__ tw1g,
+                                                     const typename CTf<T>::type* __restrict__ log_,
+                                                     const typename CTf<T>::type* __restrict__ hig, int lo_bits,
+                                                     int n_hi)
+{
+    using C = typename CTf<T>::type;
+    extern __shared__ __align__(16) char smem_raw[];
+    C* tw1 = reinterpret_cast<C*>(smem_raw);
+    C* lo = tw1 + L1;
+    C* hi = lo + (1 << lo_bits);
+    C* sh = hi + n_hi;
+    const int blk = B * CC + 1;
+    for (int i = threadIdx.x; i < L1; i += blockDim.x) tw1[i] = tw1g[i];
+    for (int i = threadIdx.x; i < (1 << lo_bits); i += blockDim.x) lo[i] = log_[i];
+    for (int i = threadIdx.x; i < n_hi; i += blockDim.x) hi[i] = hig[i];
+    C* z = reinterpret_cast<C*>(grid + (int64_t)blockIdx.y * grid_stride);
+    const int c0 = blockIdx.x * CC;
+    const int c = (int)threadIdx.x % CC, r = (int)threadIdx.x / CC;
+    const int col = c0 + c;
+    __syncthreads();
+    if (r < B && col < L2) {
+        switch (A) {
+#define MM_CASE_A(n) case n: col_step_a<T, n>(z, L2p, B, r, col, tw1, sh, blk, r * CC + c); break;
+            MM_CODELETS(MM_CASE_A)
+#undef MM_CASE_A
+        }
+    }
+    __syncthreads();
+    if (r < A && col < L2) {
+        switch (B) {
+#define MM_CASE_B(n) case n: col_step_b<T, n>(z, L2p, A, r, col, CC, sh, blk, c, lo, hi, lo_bits); break;
+            MM_CODELETS(MM_CASE_B)
+#undef MM_CASE_B
+        }
+    }
+}
+
+// ---------------------------------------------------------------- row pass
+template <typename T, int A>
+__device__ __forceinline__ void row_step_a(const typename CTf<T>::type* row, int B, int nb,
+                                           const typename CTf<T>::type* tw2, typename CTf<T>::type* shrow)
+{
+    using C = typename CTf<T>::type;
+    C x[A];
+#pragma unroll
+    for (int a = 0; a < A; ++a) x[a] = row[B * a + nb];
+    dft_reg<T, A>(x);
+#pragma unroll
+    for (int a = 0; a < A; ++a) shrow[a * B + nb] = a ? cmulf(x[a], tw2[nb * a]) : x[a];
+}
+
+// Step B of one row: reads block ka of the row into registers; after the barrier
+// the caller stores the outputs (natural positions ka + A k_b) from y.
+template <typename T, int B>
+__device__ __forceinline__ void row_step_b(const typename CTf<T>::type* shrow, int ka, typename CTf<T>::type* y)
+{
+#pragma unroll
+    for (int b = 0; b < B; ++b) y[b] = shrow[ka * B + b];
+    dft_reg<T, B>(y);
+}
+
+template <typename T, int B>
+__device__ __forceinline__ void row_store_b(typename CTf<T>::type* shrow, int A, int ka,
+                                            const typename CTf<T>::type* y)
+{
+#pragma unroll
+    for (int b = 0; b < B; ++b) shrow[ka + A * b] = y[b];
+}
+
+// Workgroup (row-pair block, series): rows k1 = p0 + i and their mirrors
+// (L1 - k1) mod L1 for i < RR, then for k = k1 + L1 k2 <= N
+//   X_k = (Z_k + conj Z_{L-k})/2 - (i/2) W_Mr^k (Z_k - conj Z_{L-k})
+// (Z_{L-k} sits in the mirror row at column L2-1-k2, or (L2-k2) mod L2 when
+// k1 = 0), times the deconvolution factor.  LDS: tw2 (L2), the split W_Mr
+// table, then 2 RR rows of L2 + 1 values.
+template <typename T>
+__global__ __launch_bounds__(512) void k_fft_rows_ab(const T* __restrict__ grid, int64_t grid_stride, int L1,
+                                                     int L2, int L2p, int A, int B, int RR,
+                                                     const typename CTf<T>::type* __restrict__ tw2g,
+                                                     const typename CTf<T>::type* __restrict__ log_,
+                                                     const typename CTf<T>::type* __restrict__ hig, int lo_bits,
+                                                     int n_hi, const T* __restrict__ dfac, int N,
+                                                     typename CTf<T>::type* __restrict__ coef, int64_t ldc, int s_out)
+{
+    using C = typename CTf<T>::type;
+    extern __shared__ __align__(16) char smem_raw[];
+    C* tw2 = reinterpret_cast<C*>(smem_raw);
+    C* lo = tw2 + L2;
+    C* hi = lo + (1 << lo_bits);
+    C* sh = hi + n_hi;
+    const int rs = L2 + 1;
+    for (int i = threadIdx.x; i < L2; i += blockDim.x) tw2[i] = tw2g[i];
+    for (int i = threadIdx.x; i < (1 << lo_bits); i += blockDim.x) lo[i] = log_[i];
+    for (int i = threadIdx.x; i < n_hi; i += blockDim.x) hi[i] = hig[i];
+    const C* Y = reinterpret_cast<const C*>(grid + (int64_t)blockIdx.y * grid_stride);
+    C* out = coef + (int64_t)(s_out + blockIdx.y) * ldc;
+    const int P = L1 / 2 + 1;
+    const int p0 = blockIdx.x * RR;
+    const int nr = min(RR, P - p0);
+    // LDS row 2i: matrix row p0 + i; row 2i + 1: its mirror
+    auto mrow = [&](int r) { const int p = p0 + (r >> 1); return (r & 1) ? (L1 - p) % L1 : p; };
+    __syncthreads();
+    {
+        const int nb = (int)threadIdx.x % B, r = (int)threadIdx.x / B;
+        if (r < 2 * nr) {
+            const C* row = Y + (int64_t)mrow(r) * L2p;
+            switch (A) {
+#define MM_CASE_A(n) case n: row_step_a<T, n>(row, B, nb, tw2, sh + r * rs); break;
+                MM_CODELETS(MM_CASE_A)
+#undef MM_CASE_A
+            }
+        }
+    }
+    __syncthreads();
+    {
+        const int ka = (int)threadIdx.x % A, r = (int)threadIdx.x / A;
+        C y[32];
+        const bool act = r < 2 * nr;
+        if (act) {
+            switch (B) {
+#define MM_CASE_B(n) case n: row_step_b<T, n>(sh + r * rs, ka, y); break;
+                MM_CODELETS(MM_CASE_B)
+#undef MM_CASE_B
+            }
+        }
+        __syncthreads();
+        if (act) {
+            switch (B) {
+#define MM_CASE_S(n) case n: row_store_b<T, n>(sh + r * rs, A, ka, y); break;
+                MM_CODELETS(MM_CASE_S)
+#undef MM_CASE_S
+            }
+        }
+    }
+    __syncthreads();
+    const int total = 2 * RR * L2;
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+        const int i = idx % RR;
+        const int t2 = idx / RR;
+        const int side = t2 & 1, k2 = t2 >> 1;
+        const int p = p0 + i;
+        if (i >= nr) continue;
+        const int rowA = p, rowB = (L1 - p) % L1;
+        if (side && rowB == rowA) continue;
+        const int k1 = side ? rowB : rowA;
+        const int64_t k = (int64_t)k1 + (int64_t)L1 * k2;
+        if (k > N) continue;
+        const int k2m = (k1 == 0) ? (k2 == 0 ? 0 : L2 - k2) : (L2 - 1 - k2);
+        const C Zk = sh[(2 * i + side) * rs + k2];
+        const C Zm = sh[(2 * i + 1 - side) * rs + k2m];
+        const C Av = C{Zk.x + Zm.x, Zk.y - Zm.y};
+        const C Bv = C{Zk.x - Zm.x, Zk.y + Zm.y};
+        const C WB = cmulf(tw_split(lo, hi, (int)k, lo_bits), Bv);
+        const T d = dfac[k] * (T)0.5;
+        out[k] = C{(Av.x + WB.y) * d, (Av.y - WB.x) * d};
+    }
+}
+
+// FP64 tables of the two passes: W_L1^j, W_L2^j, the split W_L and W_Mr tables.
+template <typename T>
+__global__ void k_fft_tables(int L1, int L2, int L, int Mr, int lo_bits, int n_hi_L, int n_hi_M,
+                             typename CTf<T>::type* tw1, typename CTf<T>::type* tw2,
+                             typename CTf<T>::type* Llo, typename CTf<T>::type* Lhi,
+                             typename CTf<T>::type* Mlo, typename CTf<T>::type* Mhi)
+{
+    using C = typename CTf<T>::type;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    auto tw = [](int64_t j, int64_t n) {
+        double s, c;
+        sincospi(2.0 * (double)(j % n) / (double)n, &s, &c);
+        return C{(T)c, (T)-s};
+    };
+    const int LO = 1 << lo_bits;
+    if (i < L1) { tw1[i] = tw(i, L1); return; }
+    i -= L1;
+    if (i < L2) { tw2[i] = tw(i, L2); return; }
+    i -= L2;
+    if (i < LO) { Llo[i] = tw(i, L); Mlo[i] = tw(i, Mr); return; }
+    i -= LO;
+    if (i < n_hi_L) { Lhi[i] = tw(i * LO, L); return; }
+    i -= n_hi_L;
+    if (i < n_hi_M) { Mhi[i] = tw(i * LO, Mr); return; }
+}
+
+// ---------------------------------------------------------------- host side
+bool fft_ab_split(int n, int max_codelet, int* A, int* B)
+{
+    static const int sizes[] = {1, 2, 3, 4, 5, 6, 8, 9, 10, 12, 15, 16, 18, 20, 24, 25, 27, 30, 32};
+    int best = -1;
+    for (int a : sizes)
+        for (int b : sizes)
+            if (a * b == n && a <= b && b <= max_codelet && (best < 0 || b < best)) {
+                best = b;
+                *A = a;
+                *B = b;
+            }
+    return best > 0;
+}
+
+size_t fft_ab_lds_cols(const Plan& p)
+{
+    const size_t cs = p.prec == MM_MIXED ? 8 : 16;
+    return cs * ((size_t)p.L1 + (1u << p.tw_lo_bits) + p.tw_hi_L + (size_t)p.A1 * (p.B1 * p.CC + 1));
+}
+
+size_t fft_ab_lds_rows(const Plan& p)
+{
+    const size_t cs = p.prec == MM_MIXED ? 8 : 16;
+    return cs * ((size_t)p.L2 + (1u << p.tw_lo_bits) + p.tw_hi_M + 2 * (size_t)p.RR * (p.L2 + 1));
+}
+
+static int round64(int x) { return (x + 63) & ~63; }
+
+template <typename T>
+static hipError_t fft_ab_t(const Plan& p, const NufftWs& w, char* ws, int32_t s_begin, int32_t s_count, T* grid,
+                           int64_t gstride, void* coef, int64_t ldc, hipStream_t st)
+{
+    using C = typename CTf<T>::type;
+    const int t1 = round64(p.CC * std::max(p.A1, p.B1));
+    prof_begin("k_fft_cols", st);
+    hipLaunchKernelGGL(k_fft_cols_ab<T>, dim3((p.L2 + p.CC - 1) / p.CC, s_count), dim3(t1), fft_ab_lds_cols(p), st,
+                       grid, gstride, p.L1, p.L2, p.L2p, p.A1, p.B1, p.CC, (const C*)(ws + w.tw1),
+                       (const C*)(ws + w.tLlo), (const C*)(ws + w.tLhi), p.tw_lo_bits, p.tw_hi_L);
+    prof_end("k_fft_cols", st);
+    const int P = p.L1 / 2 + 1;
+    const int t2 = round64(std::max(2 * p.RR * std::max(p.A2, p.B2), 64));
+    prof_begin("k_fft_rows", st);
+    hipLaunchKernelGGL(k_fft_rows_ab<T>, dim3((P + p.RR - 1) / p.RR, s_count), dim3(t2), fft_ab_lds_rows(p), st,
+                       grid, gstride, p.L1, p.L2, p.L2p, p.A2, p.B2, p.RR, (const C*)(ws + w.tw2),
+                       (const C*)(ws + w.tMlo), (const C*)(ws + w.tMhi), p.tw_lo_bits, p.tw_hi_M,
+                       (const T*)(ws + w.dfac), p.N, (C*)coef, ldc, s_begin);
+    prof_end("k_fft_rows", st);
+    return hipGetLastError();
+}
+
+hipError_t launch_fft_ab(const Plan& p, const NufftWs& w, char* ws, int32_t s_begin, int32_t s_count, void* grid,
+                         int64_t gstride, void* coef, int64_t ldc, hipStream_t st)
+{
+    if (p.prec == MM_MIXED)
+        return fft_ab_t<float>(p, w, ws, s_begin, s_count, (float*)grid, gstride, coef, ldc, st);
+    return fft_ab_t<double>(p, w, ws, s_begin, s_count, (double*)grid, gstride, coef, ldc, st);
+}
+
+hipError_t launch_fft_ab_tables(const Plan& p, const NufftWs& w, char* ws, hipStream_t st)
+{
+    const int64_t total = (int64_t)p.L1 + p.L2 + (1 << p.tw_lo_bits) + p.tw_hi_L + p.tw_hi_M;
+    const int blocks = (int)((total + 255) / 256);
+    if (p.prec == MM_MIXED)
+        hipLaunchKernelGGL(k_fft_tables<float>, dim3(blocks), dim3(256), 0, st, p.L1, p.L2, p.L, p.Mr,
+                           p.tw_lo_bits, p.tw_hi_L, p.tw_hi_M, (float2*)(ws + w.tw1), (float2*)(ws + w.tw2),
+                           (float2*)(ws + w.tLlo), (float2*)(ws + w.tLhi), (float2*)(ws + w.tMlo),
+                           (float2*)(ws + w.tMhi));
+    else
+        hipLaunchKernelGGL(k_fft_tables<double>, dim3(blocks), dim3(256), 0, st, p.L1, p.L2, p.L, p.Mr,
+                           p.tw_lo_bits, p.tw_hi_L, p.tw_hi_M, (double2*)(ws + w.tw1), (double2*)(ws + w.tw2),
+                           (double2*)(ws + w.tLlo), (double2*)(ws + w.tLhi), (double2*)(ws + w.tMlo),
+                           (double2*)(ws + w.tMhi));
+    return hipGetLastError();
+}
+
+}  // namespace mm

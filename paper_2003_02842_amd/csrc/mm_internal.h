@@ -71,6 +71,13 @@ struct Plan {
     FFTDesc F1, F2;
     int CB;              // columns per block of the column pass
     int R;               // row pairs per block of the row pass
+    // two-pass sub-transforms with one LDS exchange (mm_fft.hip): L1 = A1 B1, L2 = A2 B2
+    int fft_ab;          // 1: both sub-lengths split into codelet sizes <= 32
+    int A1, B1, A2, B2;
+    int CC;              // columns per block of the column pass
+    int RR;              // row pairs per block of the row pass
+    int tw_lo_bits;      // split twiddle tables W^m = lo[m mod 2^bits] hi[m >> bits]
+    int tw_hi_L, tw_hi_M;
     int tile;            // cells per spreading tile: 1024, 2048 or 4096 (256 threads x 4, 8, 16 cells)
     int fused;           // 1: single-workgroup LDS-resident NUFFT per series
     int fused_threads;
@@ -85,6 +92,7 @@ void gauss_legendre_pos(int n_pos, double* x, double* w);   // nodes/weights on 
 // Workspace layout of one mm_nufft1 call.
 struct NufftWs {
     size_t tw1, tw2, twL, twM, rev1, pos2, dfac, flag, ranges, grid, total;
+    size_t tLlo, tLhi, tMlo, tMhi;   // split twiddle tables of the two-pass FFT
     int S_grid;   // series whose grids are resident at once
 };
 NufftWs nufft_workspace(const Plan& p, int32_t S);
@@ -100,6 +108,14 @@ hipError_t launch_nufft_tiled(const Plan& p, const NufftWs& w, char* ws, int32_t
 hipError_t launch_nufft_fused(const Plan& p, const NufftWs& w, char* ws, int32_t S, const int64_t* offsets,
                               const double* t, const void* dp, int dp_fp64, double t0, double T,
                               void* coef, int64_t ldc, hipStream_t st);
+
+// Two-pass grid FFT with one LDS exchange per pass (mm_fft.hip).
+bool fft_ab_split(int n, int max_codelet, int* A, int* B);
+size_t fft_ab_lds_cols(const Plan& p);
+size_t fft_ab_lds_rows(const Plan& p);
+hipError_t launch_fft_ab_tables(const Plan& p, const NufftWs& w, char* ws, hipStream_t st);
+hipError_t launch_fft_ab(const Plan& p, const NufftWs& w, char* ws, int32_t s_begin, int32_t s_count, void* grid,
+                         int64_t gstride, void* coef, int64_t ldc, hipStream_t st);
 
 // Contraction launchers (mm_cov.hip).
 struct Cutoffs {

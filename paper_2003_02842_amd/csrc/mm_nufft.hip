@@ -790,7 +790,9 @@ hipError_t launch_prep(const Plan& p, const NufftWs& w, char* ws, hipStream_t st
                            p.F2, gl, (double2*)(ws + w.tw1), (double2*)(ws + w.tw2), (double2*)(ws + w.twL),
                            (double2*)(ws + w.twM), (int*)(ws + w.rev1), (int*)(ws + w.pos2), (double*)(ws + w.dfac));
     prof_end("k_prep", st);
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && p.fft_ab) e = launch_fft_ab_tables(p, w, ws, st);
+    return e;
 }
 
 hipError_t launch_validate(int32_t S, const int64_t* offsets, const double* t, const void* dp, int dp_fp64,
@@ -865,6 +867,7 @@ static hipError_t nufft_tiled_t(const Plan& p, const NufftWs& w, char* ws, int32
         launch_spread_k<T, float>(p, s_count, t, (const float*)dp, t0, T_, ranges, tiles, grid, gstride, st);
     prof_end("k_spread", st);
 
+    if (p.fft_ab) return launch_fft_ab(p, w, ws, s_begin, s_count, grid, gstride, coef, ldc, st);
     const int cbs = ilog2(p.CB);
     const size_t lds1 = (size_t)(p.L1 + p.CB * (p.L1 | 1)) * sizeof(C) + (size_t)((p.L1 + 3) & ~3) * 4;
     prof_begin("k_fft_cols", st);

@@ -364,6 +364,25 @@ mm_status make_plan(int32_t N, mm_kernel kernel, double tol, mm_prec prec, const
     while (R > 1 && (size_t)(2 * R * (L2 | 1) + L2) * cs + (size_t)((L2 + 3) & ~3) * 4 > budget) R >>= 1;
     while (R > 1 && R / 2 >= P) R >>= 1;         // stays a power of two
     p->R = R;
+    // two-pass sub-transforms with register codelets when both lengths split
+    {
+        const int maxc = 32;
+        p->fft_ab = fft_ab_split(L1, maxc, &p->A1, &p->B1) && fft_ab_split(L2, maxc, &p->A2, &p->B2);
+        if (tune && tune->fft_generic == 1) p->fft_ab = 0;
+        int bits = 0;
+        while ((1ll << (2 * bits)) < (long long)p->L) ++bits;
+        p->tw_lo_bits = bits;
+        p->tw_hi_L = (int)((p->L + (1 << bits) - 1) >> bits);
+        p->tw_hi_M = p->tw_hi_L;
+        p->CC = (prec == MM_MIXED) ? 16 : 8;      // 128-byte row segments
+        while (p->CC > 1 && p->CC / 2 >= L2) p->CC >>= 1;
+        const size_t lds_max = 52 * 1024;
+        p->RR = 8;
+        while (p->RR > 1 && (fft_ab_lds_rows(*p) > lds_max || 2 * p->RR * std::max(p->A2, p->B2) > 512)) --p->RR;
+        while (p->RR > 1 && p->RR - 1 >= L1 / 2 + 1) --p->RR;
+        while (p->fft_ab && p->CC > 1 && fft_ab_lds_cols(*p) > lds_max) p->CC >>= 1;
+        if (p->fft_ab && (fft_ab_lds_rows(*p) > 64 * 1024 || fft_ab_lds_cols(*p) > 64 * 1024)) p->fft_ab = 0;
+    }
     int tile = (prec == MM_MIXED) ? 2048 : 1024;
     if (tune && tune->tile > 0) tile = tune->tile <= 1024 ? 1024 : (tune->tile <= 2048 ? 2048 : 4096);
     p->tile = tile;
@@ -386,6 +405,10 @@ NufftWs nufft_workspace(const Plan& p, int32_t S)
     w.rev1 = o; o += al(4 * (size_t)p.L1);
     w.pos2 = o; o += al(4 * (size_t)p.L2);
     w.dfac = o; o += al(rs * (size_t)(p.N + 1));
+    w.tLlo = o; o += al(2 * rs * ((size_t)1 << p.tw_lo_bits));
+    w.tLhi = o; o += al(2 * rs * (size_t)p.tw_hi_L);
+    w.tMlo = o; o += al(2 * rs * ((size_t)1 << p.tw_lo_bits));
+    w.tMhi = o; o += al(2 * rs * (size_t)p.tw_hi_M);
     w.flag = o; o += 256;
     w.S_grid = (p.prec == MM_MIXED && !p.fused) ? S : (p.fused ? 0 : 1);
     const size_t tiles = (size_t)(p.Mr + p.tile - 1) / p.tile;

@@ -173,3 +173,23 @@ def test_epps_replicates_sweep(mm, basis):
         for g in range(w.G):
             assert relfro(S[q, g], So[q, g]) <= MIXED_BAR
             assert relfro(R[q, g], Ro[q, g]) <= MIXED_BAR
+
+
+# ---------------------------------------- both grid-FFT implementations agree
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed", 1e-6)])
+@pytest.mark.parametrize("N", [1, 2, 7, 100, 3000])
+def test_generic_and_codelet_fft_paths(mm, prec, tol, N):
+    """The register-codelet two-pass FFT and the generic in-LDS radix passes
+    (mm_tuning.fft_generic = 1) both meet the bar against the oracle, from the
+    smallest grids (Mr = 8) up to several thousand points."""
+    w = synth.random_events(6, 0, 400, seed=31 + N, dp_dtype=torch.float64 if prec == "fp64" else torch.float32)
+    ref = oracle_coef(w, N)
+    bar = tol * 2 + (2e-7 if prec == "mixed" else 1e-14)
+    info = mm.plan_query(N, "es", tol, prec)
+    for tune in (None, {"fft_generic": 1}):
+        c = gpu_coef(mm, w, N, "es", tol, prec, tune)
+        err = series_rel_l2(c, ref)
+        counts = (w.offsets[1:] - w.offsets[:-1]).tolist()
+        for s, n in enumerate(counts):
+            if n:
+                assert err[s] <= bar, (tune, info["Mr"], s, err[s])
