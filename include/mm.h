@@ -181,6 +181,39 @@ mm_status mm_estimate(int32_t G, int32_t D, const int64_t* offsets, const double
 /* Synchronises the device and frees every graph mm_estimate recorded. */
 mm_status mm_graph_cache_clear(void);
 
+/* Result of mm_matrix_to_csr (host). */
+typedef struct {
+    int64_t E;                 /* returns written (CSR length) */
+    int32_t N;                 /* Nyquist cutoff min_i N_i (INT32_MAX if no asset has two observations) */
+    double t0, T;              /* time window: min and max observation time over all assets */
+} mm_csr_info;
+
+/* Bytes of device workspace mm_matrix_to_csr needs (two n*D FP64 staging arrays
+ * plus per-asset scalars). */
+mm_status mm_matrix_to_csr_workspace_size(int64_t n, int32_t D, size_t* bytes /* host */);
+
+/* The MM algorithm's own input form (its inputs P and T; steps I.1-I.2 and
+ * F.1-F.3; the time-rescaling and Nyquist-frequency algorithms): n x D matrices of
+ * prices and times, column-major (column i = asset i, element (h, i) at i*ld + h,
+ * ld >= n), NaN where an asset has no observation.  An observation counts when
+ * both its price and its time are finite.  Writes the CSR input of mm_nufft1:
+ *   offsets  int64[D+1]; asset i owns returns offsets[i] .. offsets[i+1]-1
+ *   t        float64[cap]: time of the left observation of each return
+ *   dp       float32 or float64[cap]: log p_{h+1} - log p_h (natural log)
+ *   nyq      int32[D]: N_i = floor((t_max - t_min) / (2 dt_i)), dt_i the smallest gap between
+ *            consecutive observation times of asset i (the Nyquist-frequency algorithm on
+ *            times rescaled to [0, 2 pi]); INT32_MAX for an asset with fewer than two
+ *            observations
+ *   info     host: returns written, N = min_i N_i and the window (t0, T) = (t_min, t_max)
+ *            to pass to mm_nufft1
+ * All arrays are device memory; cap = n*D always suffices.  Synchronises `stream`.
+ * Errors: MM_ERR_ARG; MM_ERR_DATA (a non-positive price, times not increasing within an
+ * asset, a repeated time, or fewer than two distinct times overall); MM_ERR_WORKSPACE
+ * (ws too small, or more than cap returns); MM_ERR_HIP. */
+mm_status mm_matrix_to_csr(int64_t n, int32_t D, const double* P, const double* Tm, int64_t ld, int64_t* offsets,
+                           double* t, void* dp, int32_t dp_is_fp64, int64_t cap, int32_t* nyq, void* ws,
+                           size_t ws_bytes, mm_csr_info* info /* host */, void* stream);
+
 /* Human-readable text of a status (static storage). */
 const char* mm_status_string(mm_status s);
 

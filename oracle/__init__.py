@@ -117,3 +117,41 @@ def estimate(w, Ns=None, basis: int = DIRICHLET):
     coef = coeffs_batch(w.offsets, w.t, w.dp, w.t0, w.T, max(Ns))
     S, R = cov(coef, w.G, w.D, Ns, basis)
     return coef, S, R
+
+
+INT32_MAX = 2 ** 31 - 1
+
+
+def matrix_to_csr(P, T):
+    """The MM algorithm's input form to CSR returns (steps F.1-F.3), the window of
+    the time-rescaling algorithm and the cutoffs of the Nyquist-frequency
+    algorithm, in plain numpy.
+
+    P, T: (n, D) arrays, NaN where asset i has no observation; an observation
+    counts when both entries are finite.  Window: min and max of all counted
+    times.  Asset i: its counted times in row order, log prices, returns
+    log p_{h+1} - log p_h at time t_h; dt_i = smallest gap between consecutive
+    times; N_i = floor((t_max - t_min) / (2 dt_i)) (the algorithm's
+    floor(N_0/2) with N_0 = 2 pi / dt on times rescaled to [0, 2 pi]), capped
+    at 2^31 - 1; N = min_i N_i.  Returns (offsets, t, dp, nyq, N, (t0, T))."""
+    P = np.asarray(P, dtype=np.float64)
+    T = np.asarray(T, dtype=np.float64)
+    n, D = P.shape
+    valid = np.isfinite(P) & np.isfinite(T)
+    t0, t1 = float(T[valid].min()), float(T[valid].max())
+    offsets, ts, dps, nyq = [0], [], [], []
+    for i in range(D):
+        tv = T[valid[:, i], i]
+        lp = np.log(P[valid[:, i], i])
+        if tv.size >= 2:
+            ts.append(tv[:-1])
+            dps.append(lp[1:] - lp[:-1])
+            gaps = tv[1:] - tv[:-1]
+            # cutoffs are int32 at the library boundary: larger values are capped there
+            nyq.append(min(int(np.floor((t1 - t0) / (2.0 * gaps.min()))), INT32_MAX))
+        else:
+            nyq.append(INT32_MAX)
+        offsets.append(offsets[-1] + max(tv.size - 1, 0))
+    t = np.concatenate(ts) if ts else np.zeros(0)
+    dp = np.concatenate(dps) if dps else np.zeros(0)
+    return np.array(offsets, dtype=np.int64), t, dp, np.array(nyq, dtype=np.int64), min(nyq), (t0, t1)

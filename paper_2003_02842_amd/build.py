@@ -20,7 +20,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libmm.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["mm_plan.cpp", "mm_api.cpp", "mm_nufft.hip", "mm_fft.hip", "mm_cov.hip"]
+SOURCES = ["mm_plan.cpp", "mm_api.cpp", "mm_nufft.hip", "mm_fft.hip", "mm_cov.hip", "mm_input.hip"]
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include")]
 DEVICE = ["-x", "hip", "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

@@ -386,6 +386,47 @@ mm_status mm_graph_cache_clear(void)
     return MM_OK;
 }
 
+mm_status mm_matrix_to_csr_workspace_size(int64_t n, int32_t D, size_t* bytes)
+{
+    if (!bytes || n < 1 || D < 1) return MM_ERR_ARG;
+    *bytes = input_workspace(n, D).total;
+    return MM_OK;
+}
+
+mm_status mm_matrix_to_csr(int64_t n, int32_t D, const double* P, const double* Tm, int64_t ld, int64_t* offsets,
+                           double* t, void* dp, int32_t dp_is_fp64, int64_t cap, int32_t* nyq, void* ws,
+                           size_t ws_bytes, mm_csr_info* info, void* stream)
+{
+    if (n < 1 || D < 1 || ld < n || !P || !Tm || !offsets || !nyq || !info || cap < 0) return MM_ERR_ARG;
+    if ((cap > 0 && (!t || !dp)) || (dp_is_fp64 != 0 && dp_is_fp64 != 1)) return MM_ERR_ARG;
+    if (D > 65535) return MM_ERR_UNSUPPORTED;
+    const InputWs w = input_workspace(n, D);
+    if (!ws || ws_bytes < w.total) return MM_ERR_WORKSPACE;
+    if (((uintptr_t)ws & 255) != 0) return MM_ERR_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    char* wsb = (char*)ws;
+    if (launch_input(n, D, P, Tm, ld, offsets, t, dp, dp_is_fp64, nyq, w, wsb, st) != hipSuccess) return MM_ERR_HIP;
+    int64_t meta[6];
+    if (hipMemcpyAsync(meta, wsb + w.meta, sizeof(meta), hipMemcpyDeviceToHost, st) != hipSuccess) return MM_ERR_HIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return MM_ERR_HIP;
+    const int64_t E = meta[0];
+    if ((int)meta[2] != 0) return MM_ERR_DATA;
+    if (E > cap) return MM_ERR_WORKSPACE;
+    if (launch_input_returns(D, E, offsets, t, dp, dp_is_fp64, nyq, w, wsb, st) != hipSuccess) return MM_ERR_HIP;
+    if (hipMemcpyAsync(meta, wsb + w.meta, sizeof(meta), hipMemcpyDeviceToHost, st) != hipSuccess) return MM_ERR_HIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return MM_ERR_HIP;
+    double window[2];
+    memcpy(window, &meta[4], sizeof(window));
+    int32_t N;
+    memcpy(&N, &meta[3], sizeof(N));
+    if ((int)meta[2] != 0 || !(window[1] > window[0])) return MM_ERR_DATA;
+    info->E = E;
+    info->N = N;
+    info->t0 = window[0];
+    info->T = window[1];
+    return MM_OK;
+}
+
 mm_status mm_profile_enable(int32_t on)
 {
     std::lock_guard<std::mutex> lk(g_prof_mu);

@@ -258,12 +258,16 @@ __global__ __launch_bounds__(256) void k_syrk_mfma(const uint16_t* __restrict__ 
                 fbh[b] = *(const bf16x8*)&sBh[c * SLD + kof];
                 fbl[b] = *(const bf16x8*)&sBl[c * SLD + kof];
             }
+            // the three products of one block are four MFMAs apart
             for (int a = 0; a < 2; ++a)
-                for (int b = 0; b < 2; ++b) {
+                for (int b = 0; b < 2; ++b)
                     acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[a], fbh[b], acc[a][b], 0, 0, 0);
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b)
                     acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[a], fbl[b], acc[a][b], 0, 0, 0);
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b)
                     acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fal[a], fbh[b], acc[a][b], 0, 0, 0);
-                }
         }
         __syncthreads();
     }
@@ -277,18 +281,149 @@ __global__ __launch_bounds__(256) void k_syrk_mfma(const uint16_t* __restrict__ 
             }
 }
 
-// Sum of the k-range partials of one 64x64 quarter of a lower-triangle tile,
-// written to Sigma at (i, j) and, through an LDS transpose, at (j, i).
-__global__ __launch_bounds__(256) void k_syrk_reduce(const float* __restrict__ partial, int nsplit, int ntiles, int D,
-                                                     float* __restrict__ cov)
+// Large-D form: one workgroup = one lower-triangle 256x256 tile over one k-range;
+// each of the four waves owns a 128x128 quadrant (4 x 4 blocks of 32 x 32, 256
+// accumulators per lane).  Stages of 32 k move global -> registers -> LDS with
+// two LDS buffers, so the loads of stage s+1 are in flight while stage s runs on
+// MFMA.  LDS rows are 64 bytes (4 chunks of 16 B); chunk c of row r sits at
+// position c ^ ((r >> 2) & 3), which keeps every 16-lane group of a 16-byte
+// fragment read on distinct banks.  A diagonal tile stages its one panel once
+// and leaves the quadrant above the diagonal idle.
+constexpr int T2 = 256;
+constexpr int SK2 = 32;
+
+__device__ __forceinline__ int swz(int row, int chunk) { return (row << 2) | (chunk ^ ((row >> 2) & 3)); }
+
+// One stage (32 k) of a wave's 128x128 quadrant from LDS buffer L: per 16 k, the
+// four A row blocks (hi, lo) stay in registers while each B block streams through.
+__device__ __forceinline__ void syrk256_stage(const uint4* __restrict__ L, int ba, int wy, int wx, int lane,
+                                              f32x16 (&acc)[4][4])
 {
-    __shared__ float tileT[64][65];
-    const int t = blockIdx.x >> 2, quad = blockIdx.x & 3;
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+        const int ch = 2 * ks + (lane >> 5);
+        bf16x8 fah[4], fal[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const int r = wy * 128 + a * 32 + (lane & 31);
+            uint4 vh = L[0 * T2 * 4 + swz(r, ch)], vl = L[1 * T2 * 4 + swz(r, ch)];
+            fah[a] = *reinterpret_cast<bf16x8*>(&vh);
+            fal[a] = *reinterpret_cast<bf16x8*>(&vl);
+        }
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int r = wx * 128 + b * 32 + (lane & 31);
+            uint4 vh = L[ba * T2 * 4 + swz(r, ch)], vl = L[(ba + 1) * T2 * 4 + swz(r, ch)];
+            const bf16x8 fbh = *reinterpret_cast<bf16x8*>(&vh), fbl = *reinterpret_cast<bf16x8*>(&vl);
+            // the three products of one block are four MFMAs apart, so no MFMA waits on
+            // the accumulator of the one before it
+#pragma unroll
+            for (int a = 0; a < 4; ++a) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[a], fbh, acc[a][b], 0, 0, 0);
+#pragma unroll
+            for (int a = 0; a < 4; ++a) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[a], fbl, acc[a][b], 0, 0, 0);
+#pragma unroll
+            for (int a = 0; a < 4; ++a) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fal[a], fbh, acc[a][b], 0, 0, 0);
+        }
+    }
+}
+
+// Stage loads: one global_load_lds_dwordx4 per wave fills 1 KB (16 rows of an
+// array); lane p lands in slot p, i.e. row R0 + (p >> 2), physical chunk p & 3, so
+// it fetches logical chunk (p & 3) ^ ((row >> 2) & 3).  Byte offsets fit 32 bits.
+__device__ __forceinline__ void syrk256_load(uint4* L, const char* const (&src)[4], const uint32_t (&goff)[4],
+                                             uint32_t kbyte, int wave, bool diag)
+{
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        if (a >= 2 && diag) break;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            __builtin_amdgcn_global_load_lds(src[a] + goff[q] + kbyte, L + (a * T2 + 16 * (4 * wave + q)) * 4, 16,
+                                             0, 0);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_syrk_mfma256(const uint16_t* __restrict__ hi,
+                                                      const uint16_t* __restrict__ lo, int64_t Kp, int64_t kchunk,
+                                                      int ntiles, int nsplit, float* __restrict__ partial)
+{
+    __shared__ uint4 lds0[4 * T2 * 4];   // [array: A hi, A lo, B hi, B lo][row][chunk], even stages
+    __shared__ uint4 lds1[4 * T2 * 4];   // odd stages
+    const int split = (int)(blockIdx.x % (unsigned)nsplit);
+    const int t = (int)(blockIdx.x / (unsigned)nsplit);
     int bi = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
     while (bi * (bi + 1) / 2 > t) --bi;
     while ((bi + 1) * (bi + 2) / 2 <= t) ++bi;
     const int bj = t - bi * (bi + 1) / 2;
-    const int qi = (quad >> 1) * 64, qj = (quad & 1) * 64;
+    const bool diag = bi == bj;
+    const int64_t kb = (int64_t)split * kchunk;
+    const int64_t ke = min(kb + kchunk, Kp);
+    const int nst = (int)((ke - kb) / SK2);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wy = wave >> 1, wx = wave & 1;
+    const bool active = !(diag && wy == 0 && wx == 1);
+    const char* const src[4] = {(const char*)(hi + (int64_t)bi * T2 * Kp), (const char*)(lo + (int64_t)bi * T2 * Kp),
+                                (const char*)(hi + (int64_t)bj * T2 * Kp), (const char*)(lo + (int64_t)bj * T2 * Kp)};
+    uint32_t goff[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int row = 16 * (4 * wave + q) + (lane >> 2);
+        goff[q] = (uint32_t)(row * Kp + 8 * ((lane & 3) ^ ((row >> 2) & 3))) * 2u;
+    }
+    f32x16 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
+    const int ba = diag ? 0 : 2;   // arrays holding the B panel
+    const uint32_t kb0 = (uint32_t)kb * 2u;
+    if (nst > 0) syrk256_load(lds0, src, goff, kb0, wave, diag);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    for (int s = 0; s < nst; s += 2) {
+        // even stage from lds0 while odd stage s+1 loads into lds1
+        if (s + 1 < nst) syrk256_load(lds1, src, goff, kb0 + (uint32_t)(s + 1) * SK2 * 2u, wave, diag);
+        if (active) syrk256_stage(lds0, ba, wy, wx, lane, acc);
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        if (s + 1 >= nst) break;
+        if (s + 2 < nst) syrk256_load(lds0, src, goff, kb0 + (uint32_t)(s + 2) * SK2 * 2u, wave, diag);
+        if (active) syrk256_stage(lds1, ba, wy, wx, lane, acc);
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+    }
+    if (!active) return;
+    float* P = partial + ((int64_t)split * ntiles + t) * T2 * T2;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int i = wy * 128 + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const int j = wx * 128 + b * 32 + (lane & 31);
+                P[i * T2 + j] = acc[a][b][r];
+            }
+}
+
+// Sum of the k-range partials of one 64x64 sub-block of a lower-triangle tile,
+// written to Sigma at (i, j) and, through an LDS transpose, at (j, i).
+template <int TS>
+__global__ __launch_bounds__(256) void k_syrk_reduce(const float* __restrict__ partial, int nsplit, int ntiles, int D,
+                                                     float* __restrict__ cov)
+{
+    constexpr int ST = TS;
+    constexpr int QN = TS / 64;   // 64 x 64 sub-blocks per tile edge
+    __shared__ float tileT[64][65];
+    const int t = blockIdx.x / (QN * QN), quad = blockIdx.x % (QN * QN);
+    int bi = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while (bi * (bi + 1) / 2 > t) --bi;
+    while ((bi + 1) * (bi + 2) / 2 <= t) ++bi;
+    const int bj = t - bi * (bi + 1) / 2;
+    const int qi = (quad / QN) * 64, qj = (quad % QN) * 64;
+    if (bi == bj && qi < qj) return;   // above the diagonal of a diagonal tile: mirrored from below
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     const int64_t tstride = (int64_t)ntiles * ST * ST;
     const float* P = partial + (int64_t)t * ST * ST;
@@ -380,7 +515,12 @@ hipError_t launch_cov_fp64(int32_t G, int32_t D, const void* coef, int64_t ldc, 
     return hipGetLastError();
 }
 
+#ifndef MM_SYRK_BIG_TILES
+#define MM_SYRK_BIG_TILES 1
+#endif
+
 struct MfmaShape {
+    int ts;               // tile edge: 128 or 256
     int tn, ntiles, nsplit;
     int64_t Dp, Kp, kchunk;
     size_t hi, lo, partial, total;
@@ -389,10 +529,30 @@ struct MfmaShape {
 static MfmaShape mfma_shape(int32_t D, int32_t N)
 {
     MfmaShape s;
+    s.Kp = ((2ll * (N + 1) + SK - 1) / SK) * SK;
+    const int tn2 = (D + T2 - 1) / T2;
+    if (MM_SYRK_BIG_TILES && tn2 >= 4 && s.Kp / SK2 >= 64) {
+        // 256-wide tiles, about one workgroup per CU, so every tile's k-range runs
+        // concurrently and the partials stay few
+        s.ts = T2;
+        s.tn = tn2;
+        s.ntiles = s.tn * (s.tn + 1) / 2;
+        s.Dp = (int64_t)s.tn * T2;
+        s.nsplit = std::max(1, 256 / s.ntiles);
+        const int64_t per = (s.Kp + s.nsplit - 1) / s.nsplit;
+        s.kchunk = ((per + SK2 - 1) / SK2) * SK2;
+        auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+        size_t o = 0;
+        s.hi = o; o += al((size_t)s.Dp * s.Kp * 2);
+        s.lo = o; o += al((size_t)s.Dp * s.Kp * 2);
+        s.partial = o; o += al((size_t)s.nsplit * s.ntiles * T2 * T2 * 4);
+        s.total = o;
+        return s;
+    }
+    s.ts = ST;
     s.tn = (D + ST - 1) / ST;
     s.ntiles = s.tn * (s.tn + 1) / 2;
     s.Dp = (int64_t)s.tn * ST;
-    s.Kp = ((2ll * (N + 1) + SK - 1) / SK) * SK;
     // k-ranges: 8 m of them, m per XCD.  One per XCD measured fastest once the
     // tiles alone give a few hundred workgroups; small D takes more ranges (each
     // >= 8 k-stages) to occupy the chip.
@@ -432,12 +592,20 @@ hipError_t launch_cov_mfma(int32_t G, int32_t D, const void* coef, int64_t ldc, 
         hipLaunchKernelGGL(k_split_bf16, dim3(bx, s.Dp), dim3(256), 0, st, D, (int)s.Dp, cg, ldc, N, basis, s.Kp, hi, lo);
         prof_end("k_split_bf16", st);
         prof_begin("k_syrk_mfma", st);
-        hipLaunchKernelGGL(k_syrk_mfma, dim3((unsigned)(s.ntiles * s.nsplit)), dim3(256), 0, st, hi, lo, s.Kp,
-                           s.kchunk, s.ntiles, s.nsplit, part);
+        if (s.ts == T2)
+            hipLaunchKernelGGL(k_syrk_mfma256, dim3((unsigned)(s.ntiles * s.nsplit)), dim3(256), 0, st, hi, lo, s.Kp,
+                               s.kchunk, s.ntiles, s.nsplit, part);
+        else
+            hipLaunchKernelGGL(k_syrk_mfma, dim3((unsigned)(s.ntiles * s.nsplit)), dim3(256), 0, st, hi, lo, s.Kp,
+                               s.kchunk, s.ntiles, s.nsplit, part);
         prof_end("k_syrk_mfma", st);
         prof_begin("k_syrk_reduce", st);
-        hipLaunchKernelGGL(k_syrk_reduce, dim3((unsigned)(4 * s.ntiles)), dim3(256), 0, st, part, s.nsplit, s.ntiles,
-                           D, (float*)cov + (int64_t)g * D * D);
+        if (s.ts == T2)
+            hipLaunchKernelGGL(k_syrk_reduce<T2>, dim3((unsigned)(16 * s.ntiles)), dim3(256), 0, st, part, s.nsplit,
+                               s.ntiles, D, (float*)cov + (int64_t)g * D * D);
+        else
+            hipLaunchKernelGGL(k_syrk_reduce<ST>, dim3((unsigned)(4 * s.ntiles)), dim3(256), 0, st, part, s.nsplit,
+                               s.ntiles, D, (float*)cov + (int64_t)g * D * D);
         prof_end("k_syrk_reduce", st);
     }
     return hipGetLastError();

@@ -372,10 +372,14 @@ __global__ __launch_bounds__(512) void k_fft_rows_ab(const T* __restrict__ grid,
         }
     }
     __syncthreads();
-    const int total = 2 * RR * L2;
+    // RR is a power of two: row index fastest, so R consecutive k share a segment.
+    // Only columns k2 <= (N - p0)/L1 can hold a k <= N.
+    const int rr_bits = __ffs(RR) - 1;
+    const int K2 = min(L2, (N - p0) / L1 + 1);
+    const int total = 2 * RR * K2;
     for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-        const int i = idx % RR;
-        const int t2 = idx / RR;
+        const int i = idx & (RR - 1);
+        const int t2 = idx >> rr_bits;
         const int side = t2 & 1, k2 = t2 >> 1;
         const int p = p0 + i;
         if (i >= nr) continue;

@@ -117,6 +117,16 @@ hipError_t launch_fft_ab_tables(const Plan& p, const NufftWs& w, char* ws, hipSt
 hipError_t launch_fft_ab(const Plan& p, const NufftWs& w, char* ws, int32_t s_begin, int32_t s_count, void* grid,
                          int64_t gstride, void* coef, int64_t ldc, hipStream_t st);
 
+// Paper-form input (mm_input.hip): price/time matrices to CSR returns.
+struct InputWs {
+    size_t cnt, tmin, tmax, mindt, voff, meta, tv, lv, total;
+};
+InputWs input_workspace(int64_t n, int32_t D);
+hipError_t launch_input(int64_t n, int32_t D, const double* P, const double* Tm, int64_t ld, int64_t* offsets,
+                        double* t, void* dp, int dp_fp64, int32_t* nyq, const InputWs& w, char* ws, hipStream_t st);
+hipError_t launch_input_returns(int32_t D, int64_t E, int64_t* offsets, double* t, void* dp, int dp_fp64,
+                                int32_t* nyq, const InputWs& w, char* ws, hipStream_t st);
+
 // Contraction launchers (mm_cov.hip).
 struct Cutoffs {
     int n;

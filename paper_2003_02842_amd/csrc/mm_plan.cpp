@@ -13,6 +13,14 @@
 
 namespace mm {
 
+// LDS budget of one FFT workgroup and the largest row-pair block of the row pass.
+#ifndef MM_FFT_LDS_MAX
+#define MM_FFT_LDS_MAX (64 * 1024)
+#endif
+#ifndef MM_FFT_RR_MAX
+#define MM_FFT_RR_MAX 4
+#endif
+
 static const double kPi = 3.14159265358979323846264338327950288;
 
 FastDiv make_fastdiv(uint32_t d)
@@ -376,10 +384,10 @@ mm_status make_plan(int32_t N, mm_kernel kernel, double tol, mm_prec prec, const
         p->tw_hi_M = p->tw_hi_L;
         p->CC = (prec == MM_MIXED) ? 16 : 8;      // 128-byte row segments
         while (p->CC > 1 && p->CC / 2 >= L2) p->CC >>= 1;
-        const size_t lds_max = 52 * 1024;
-        p->RR = 8;
-        while (p->RR > 1 && (fft_ab_lds_rows(*p) > lds_max || 2 * p->RR * std::max(p->A2, p->B2) > 512)) --p->RR;
-        while (p->RR > 1 && p->RR - 1 >= L1 / 2 + 1) --p->RR;
+        const size_t lds_max = MM_FFT_LDS_MAX;
+        p->RR = MM_FFT_RR_MAX;                     // a power of two
+        while (p->RR > 1 && (fft_ab_lds_rows(*p) > lds_max || 2 * p->RR * std::max(p->A2, p->B2) > 512)) p->RR >>= 1;
+        while (p->RR > 1 && p->RR / 2 >= L1 / 2 + 1) p->RR >>= 1;
         while (p->fft_ab && p->CC > 1 && fft_ab_lds_cols(*p) > lds_max) p->CC >>= 1;
         if (p->fft_ab && (fft_ab_lds_rows(*p) > 64 * 1024 || fft_ab_lds_cols(*p) > 64 * 1024)) p->fft_ab = 0;
     }

@@ -28,6 +28,7 @@ _PRECS = {"fp64": PLAIN_FP64, "plain": PLAIN_FP64, "mixed": MIXED}
 
 EXPORTED = ["mm_plan_query", "mm_nufft1_workspace_size", "mm_nufft1", "mm_cov_workspace_size", "mm_cov",
             "mm_estimate_workspace_size", "mm_estimate", "mm_graph_cache_clear",
+            "mm_matrix_to_csr_workspace_size", "mm_matrix_to_csr",
             "mm_status_string", "mm_profile_enable", "mm_profile_read", "mm_profile_reset"]
 
 
@@ -35,6 +36,10 @@ class MMError(RuntimeError):
     def __init__(self, status: int, where: str):
         self.status = status
         super().__init__("%s failed: %s (status %d)" % (where, _status_text(status), status))
+
+
+class CsrInfo(ctypes.Structure):
+    _fields_ = [("E", ctypes.c_int64), ("N", ctypes.c_int32), ("t0", ctypes.c_double), ("T", ctypes.c_double)]
 
 
 class Tuning(ctypes.Structure):
@@ -69,6 +74,8 @@ def lib():
         L.mm_estimate.argtypes = [i32, i32, P, P, P, i32, f64, f64, P, i32, i32, i32, f64, i32, P, P, i64, P, P, P,
                                   sz, i32, P]
         L.mm_graph_cache_clear.argtypes = []
+        L.mm_matrix_to_csr_workspace_size.argtypes = [i64, i32, ctypes.POINTER(sz)]
+        L.mm_matrix_to_csr.argtypes = [i64, i32, P, P, i64, P, P, P, i32, i64, P, P, sz, P, P]
         L.mm_status_string.argtypes = [i32]
         L.mm_status_string.restype = ctypes.c_char_p
         L.mm_profile_enable.argtypes = [i32]
@@ -286,3 +293,34 @@ def profile_read(name=None):
     _check(lib().mm_profile_read(name.encode() if name else None, ctypes.byref(ms), ctypes.byref(n)),
            "mm_profile_read")
     return float(ms.value), int(n.value)
+
+
+def matrix_to_csr(P: torch.Tensor, T: torch.Tensor, dp_dtype=torch.float32, ws: torch.Tensor = None):
+    """The MM algorithm's input form -- (n, D) device tensors of prices and
+    times, NaN where an asset has no observation -- to CSR returns
+    (mm_matrix_to_csr).  Returns (offsets, t, dp, nyq, info) where info holds
+    E, the Nyquist cutoff N = min_i N_i and the window (t0, T)."""
+    if not (P.is_cuda and T.is_cuda) or P.dtype != torch.float64 or T.dtype != torch.float64:
+        raise TypeError("P and T must be float64 device tensors")
+    if P.shape != T.shape or P.dim() != 2:
+        raise ValueError("P and T must have the same (n, D) shape")
+    n, D = P.shape
+    Pc = P.t().contiguous()   # column-major n x D: asset i contiguous
+    Tc = T.t().contiguous()
+    dev = P.device
+    need = ctypes.c_size_t(0)
+    _check(lib().mm_matrix_to_csr_workspace_size(n, D, ctypes.byref(need)), "mm_matrix_to_csr_workspace_size")
+    if ws is None or ws.numel() < need.value:
+        ws = torch.empty(need.value, dtype=torch.uint8, device=dev)
+    cap = n * D
+    offsets = torch.empty(D + 1, dtype=torch.int64, device=dev)
+    t = torch.empty(cap, dtype=torch.float64, device=dev)
+    dp = torch.empty(cap, dtype=dp_dtype, device=dev)
+    nyq = torch.empty(D, dtype=torch.int32, device=dev)
+    info = CsrInfo()
+    st = lib().mm_matrix_to_csr(n, D, _ptr(Pc), _ptr(Tc), n, _ptr(offsets), _ptr(t), _ptr(dp),
+                                int(dp_dtype == torch.float64), cap, _ptr(nyq), _ptr(ws), ws.numel(),
+                                ctypes.byref(info), _stream())
+    _check(st, "mm_matrix_to_csr")
+    E = int(info.E)
+    return offsets, t[:E], dp[:E], nyq, {"E": E, "N": int(info.N), "t0": info.t0, "T": info.T}

@@ -238,3 +238,61 @@ def test_sweep_matches_individual_cutoffs():
         cN = oracle.coeffs_batch(w.offsets, w.t, w.dp, w.t0, w.T, N)
         SN, _ = oracle.cov(cN, 1, 3, [N], oracle.FEJER)
         np.testing.assert_allclose(S[q], SN[0], rtol=1e-14, atol=1e-18)
+
+
+# ------------------------------------------------- the MM algorithm's input form
+def test_matrix_input_hand_example():
+    """Two assets with holes: returns at the left observation, natural-log returns,
+    window = global min/max time, N_i = floor((t_max - t_min)/(2 dt_i)) (Nyquist
+    algorithm, with the footnote form floor(T / (2 dt_0)))."""
+    nan = np.nan
+    P = np.array([[100, nan], [101, 50], [nan, 51], [102, 52]], float)
+    T = np.array([[0, nan], [1, 1], [nan, 3], [4, 4]], float)
+    off, t, dp, nyq, N, win = oracle.matrix_to_csr(P, T)
+    assert off.tolist() == [0, 2, 4]
+    assert t.tolist() == [0.0, 1.0, 1.0, 3.0]
+    np.testing.assert_allclose(dp, [math.log(1.01), math.log(102 / 101), math.log(1.02), math.log(52 / 51)],
+                               rtol=1e-13)
+    assert nyq.tolist() == [2, 2] and N == 2 and win == (0.0, 4.0)
+
+
+@pytest.mark.parametrize("n", [10, 11, 1000, 1001])
+def test_matrix_input_synchronous_nyquist(n):
+    """Equally spaced observations: N = floor((n - 1)/2), i.e. half the number of
+    samples, as the paper states for synchronous data."""
+    T = np.tile(np.arange(n, dtype=float)[:, None], (1, 3))
+    P = np.exp(np.random.default_rng(n).normal(size=(n, 3)).cumsum(0) * 0.01)
+    _, _, _, nyq, N, _ = oracle.matrix_to_csr(P, T)
+    assert N == (n - 1) // 2 and all(v == (n - 1) // 2 for v in nyq)
+
+
+def test_matrix_input_degenerate_assets():
+    nan = np.nan
+    P = np.array([[nan, 10, 5], [nan, nan, 6], [nan, nan, 7.5]], float)
+    T = np.array([[0.5, 1, 0], [nan, nan, 2], [2, nan, 3]], float)
+    off, t, dp, nyq, N, win = oracle.matrix_to_csr(P, T)
+    assert off.tolist() == [0, 0, 0, 2]              # no price / one observation: no returns
+    assert nyq[0] == oracle.INT32_MAX and nyq[1] == oracle.INT32_MAX
+    assert nyq[2] == int((3 - 0) // (2 * 1)) and N == nyq[2]
+    assert win == (0.0, 3.0)
+
+
+def test_matrix_input_round_trip_of_csr_workload():
+    """A CSR workload written as NaN-padded matrices (log price = cumulative
+    returns) comes back with the same times and returns."""
+    w = synth.bivariate_async()
+    S = w.S
+    rows = max(int(w.offsets[s + 1] - w.offsets[s]) + 1 for s in range(S))
+    P = np.full((rows + 3, S), np.nan)
+    T = np.full((rows + 3, S), np.nan)
+    for s in range(S):
+        tt, dd = w.series(s)
+        tt, dd = tt.numpy(), dd.double().numpy()
+        k = tt.size
+        T[:k, s] = tt
+        T[k, s] = w.T                                     # the closing observation
+        P[:k + 1, s] = 100.0 * np.exp(np.concatenate([[0.0], np.cumsum(dd)]))
+    off, t, dp, nyq, N, win = oracle.matrix_to_csr(P, T)
+    assert off.tolist() == w.offsets.tolist()
+    np.testing.assert_array_equal(t, w.t.numpy())
+    np.testing.assert_allclose(dp, w.dp.double().numpy(), atol=1e-12)
