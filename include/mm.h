@@ -74,6 +74,9 @@ typedef struct {
     double es_beta_per_tap;    /* ES shape: beta = es_beta_per_tap * width (paper: 2.3) */
     int32_t fft_generic;       /* 1: run the grid FFT with the generic in-LDS radix passes even where both
                                   sub-lengths split into register codelets (0: auto) */
+    int32_t spread_direct;     /* MM_MIXED spreading: 1 evaluates the kernel formula at every (event, cell)
+                                  pair; 2 uses per-tap polynomials (fitted within tol/20) evaluated once per
+                                  event; 0 (auto): polynomials for Kaiser-Bessel, the formula otherwise */
 } mm_tuning;
 
 /* What the planner chose (host only, no device work). */

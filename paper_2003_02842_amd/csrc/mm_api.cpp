@@ -339,9 +339,9 @@ mm_status mm_estimate(int32_t G, int32_t D, const int64_t* offsets, const double
     key.append(reinterpret_cast<const char*>(Ns), sizeof(int32_t) * (size_t)nN);
     put(key, basis); put(key, kernel); put(key, tol); put(key, prec); put(key, ldc); put(key, ws_bytes);
     put(key, ptrs);
-    const mm_tuning tz = tune ? *tune : mm_tuning{0, 0.0, 0, 0, 0.0, 0};
+    const mm_tuning tz = tune ? *tune : mm_tuning{0, 0.0, 0, 0, 0.0, 0, 0};
     put(key, tz.width); put(key, tz.sigma); put(key, tz.tile); put(key, tz.fused); put(key, tz.es_beta_per_tap);
-    put(key, tz.fft_generic);
+    put(key, tz.fft_generic); put(key, tz.spread_direct);
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return MM_ERR_HIP;
     put(key, dev);

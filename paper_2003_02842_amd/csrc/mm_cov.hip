@@ -33,54 +33,80 @@ struct SortedCutoffs {
     int slot[kMaxCutoffs];   // output slot of each
 };
 
+// Small D (D(D+1)/2 pairs per group): one workgroup per group, KL consecutive
+// lanes per pair (KL a power of two), each lane taking every KL-th k of a 64-wide
+// chunk staged in LDS.  The k range is cut into segments at the cutoffs; at the end
+// of a segment the KL lanes of a pair add their partial sums by butterfly shuffles
+// into the running S0 = sum m_k P_k and S1 = sum m_k k P_k (m_0 = 1, m_k = 2,
+// P_k = Re c_k^(i) conj c_k^(j)), so every cutoff N reads
+//   Dirichlet (2pi)^2 S0/(2N+1),  Fejer (2pi)^2 (S0 - S1/N)/(N+1).
 template <typename CT, typename OT>
 __global__ void k_cov_small(int D, const CT* __restrict__ coef, int64_t ldc, int Nmax, SortedCutoffs cut, int basis,
-                            int G, OT* __restrict__ cov)
+                            int G, int kl_bits, OT* __restrict__ cov)
 {
     constexpr int KC = 64;
     extern __shared__ __align__(16) char smem_raw[];
     double2* sh = reinterpret_cast<double2*>(smem_raw);   // D x KC
     const int g = blockIdx.x;
+    const int KL = 1 << kl_bits;
     const int npairs = D * (D + 1) / 2;
-    int pi = -1, pj = -1;
-    if ((int)threadIdx.x < npairs) {
-        int t = threadIdx.x;
-        int i = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-        while (i * (i + 1) / 2 > t) --i;
-        while ((i + 1) * (i + 2) / 2 <= t) ++i;
+    const int pidx = (int)threadIdx.x >> kl_bits, lane = (int)threadIdx.x & (KL - 1);
+    const bool valid = pidx < npairs;
+    int pi = 0, pj = 0;
+    if (valid) {
+        int i = (int)((sqrt(8.0 * pidx + 1.0) - 1.0) * 0.5);
+        while (i * (i + 1) / 2 > pidx) --i;
+        while ((i + 1) * (i + 2) / 2 <= pidx) ++i;
         pi = i;
-        pj = t - i * (i + 1) / 2;
+        pj = pidx - i * (i + 1) / 2;
     }
-    double S0 = 0.0, S1 = 0.0;
+    double S0 = 0.0, S1 = 0.0, a0 = 0.0, a1 = 0.0;
     int q = 0;
     const double fourpi2 = kTwoPi * kTwoPi;
     for (int k0 = 0; k0 <= Nmax; k0 += KC) {
         const int kc = min(KC, Nmax + 1 - k0);
         __syncthreads();
         for (int idx = threadIdx.x; idx < D * KC; idx += blockDim.x) {
-            int d = idx / KC, kk = idx - d * KC;
+            const int d = idx / KC, kk = idx - d * KC;
             sh[idx] = (kk < kc) ? to_d2(coef[(int64_t)(g * D + d) * ldc + k0 + kk]) : make_double2(0.0, 0.0);
         }
         __syncthreads();
-        for (int kk = 0; kk < kc; ++kk) {
-            const int k = k0 + kk;
-            if (pi >= 0) {
-                double2 a = sh[pi * KC + kk], b = sh[pj * KC + kk];
-                double P = a.x * b.x + a.y * b.y;
-                double m = k ? 2.0 : 1.0;
-                S0 += m * P;
-                S1 += m * (double)k * P;
-            }
-            while (q < cut.n && cut.N[q] == k) {
-                if (pi >= 0) {
-                    const double Nd = (double)k;
-                    double v = (basis == MM_DIRICHLET) ? S0 / (2.0 * Nd + 1.0) : (S0 - S1 / Nd) / (Nd + 1.0);
-                    v *= fourpi2;
-                    OT* C = cov + ((int64_t)cut.slot[q] * G + g) * D * D;
-                    C[pi * D + pj] = (OT)v;
-                    C[pj * D + pi] = (OT)v;
+        int kk = 0;
+        while (kk < kc) {
+            // segment [kk, kend): up to and including the next cutoff, or the chunk's end
+            const bool at_cut = q < cut.n && cut.N[q] < k0 + kc;
+            const int kend = at_cut ? cut.N[q] - k0 + 1 : kc;
+            if (valid) {
+                for (int x = kk + lane; x < kend; x += KL) {
+                    const double2 u = sh[pi * KC + x], v = sh[pj * KC + x];
+                    const double P = u.x * v.x + u.y * v.y;
+                    const int k = k0 + x;
+                    const double mP = (k ? 2.0 : 1.0) * P;
+                    a0 += mP;
+                    a1 += (double)k * mP;
                 }
-                ++q;
+            }
+            kk = kend;
+            if (at_cut) {
+                for (int off = KL >> 1; off > 0; off >>= 1) {
+                    a0 += __shfl_xor(a0, off);
+                    a1 += __shfl_xor(a1, off);
+                }
+                S0 += a0;
+                S1 += a1;
+                a0 = a1 = 0.0;
+                const int kcut = k0 + kend - 1;
+                while (q < cut.n && cut.N[q] == kcut) {
+                    if (valid && lane == 0) {
+                        const double Nd = (double)kcut;
+                        double v = (basis == MM_DIRICHLET) ? S0 / (2.0 * Nd + 1.0) : (S0 - S1 / Nd) / (Nd + 1.0);
+                        v *= fourpi2;
+                        OT* C = cov + ((int64_t)cut.slot[q] * G + g) * D * D;
+                        C[pi * D + pj] = (OT)v;
+                        C[pj * D + pi] = (OT)v;
+                    }
+                    ++q;
+                }
             }
         }
     }
@@ -472,15 +498,18 @@ hipError_t launch_cov_small(int prec, int32_t G, int32_t D, const void* coef, in
 {
     SortedCutoffs sc = sort_cutoffs(cut);
     const int npairs = D * (D + 1) / 2;
-    const int threads = ((npairs + 63) / 64) * 64;
+    // lanes per pair: as many as keep the workgroup within 512 threads (<= 64, one wave)
+    int kl_bits = 0;
+    while (kl_bits < 6 && npairs * (2 << kl_bits) <= 512) ++kl_bits;
+    const int threads = std::max(64, ((npairs << kl_bits) + 63) / 64 * 64);
     const size_t lds = (size_t)D * 64 * sizeof(double2);
     prof_begin("k_cov_small", st);
     if (prec == MM_MIXED)
         hipLaunchKernelGGL((k_cov_small<float2, float>), dim3(G), dim3(threads), lds, st, D, (const float2*)coef, ldc,
-                           Nmax, sc, basis, G, (float*)cov);
+                           Nmax, sc, basis, G, kl_bits, (float*)cov);
     else
         hipLaunchKernelGGL((k_cov_small<double2, double>), dim3(G), dim3(threads), lds, st, D, (const double2*)coef,
-                           ldc, Nmax, sc, basis, G, (double*)cov);
+                           ldc, Nmax, sc, basis, G, kl_bits, (double*)cov);
     prof_end("k_cov_small", st);
     return hipGetLastError();
 }

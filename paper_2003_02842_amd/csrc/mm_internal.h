@@ -57,6 +57,24 @@ struct KernParams {
     double kb_b, kb_m, kb_inv_norm;
 };
 
+// Per-tap polynomials of the averaging kernel for the FP32 spreading path:
+// tap j of an event with cell fraction f has value sum_k c[j][k] s^k, s = f - 1/2
+// (the kernel at x = j + 1/2 - s - hw; Chebyshev interpolation, monomial form).
+// The kernel is even, so tap w-1-j is the same polynomial at -s; rows j < ceil(w/2)
+// are filled.
+constexpr int kMaxPolyTaps = 16;
+constexpr int kMaxPolyDeg = 12;
+struct PolyParams {
+    int deg;
+    float c[kMaxPolyTaps][kMaxPolyDeg + 1];
+};
+// Degree of the per-tap polynomials for a given width (enough for tol 1e-6 with
+// the ES, Kaiser-Bessel and Gaussian shapes at sigma = 2; the planner checks the fit).
+__host__ __device__ constexpr int poly_degree_for_width(int w)
+{
+    return w <= 2 ? 4 : (w <= 3 ? 5 : (w <= 5 ? 6 : (w <= 6 ? 7 : (w <= 8 ? 8 : (w <= 10 ? 9 : (w <= 12 ? 10 : (w <= 14 ? 11 : 12)))))));
+}
+
 struct Plan {
     int prec;            // mm_prec
     int kernel;          // mm_kernel
@@ -78,6 +96,9 @@ struct Plan {
     int RR;              // row pairs per block of the row pass
     int tw_lo_bits;      // split twiddle tables W^m = lo[m mod 2^bits] hi[m >> bits]
     int tw_hi_L, tw_hi_M;
+    int poly;            // 1: FP32 spreading from per-tap polynomials (mm_nufft.hip, k_spread_poly)
+    double poly_err;     // largest deviation of the polynomials from the kernel (FP64 evaluation)
+    PolyParams pp;
     int tile;            // cells per spreading tile: 1024, 2048 or 4096 (256 threads x 4, 8, 16 cells)
     int fused;           // 1: single-workgroup LDS-resident NUFFT per series
     int fused_threads;
@@ -105,6 +126,9 @@ hipError_t launch_validate(int32_t S, const int64_t* offsets, const double* t, c
 hipError_t launch_nufft_tiled(const Plan& p, const NufftWs& w, char* ws, int32_t s_begin, int32_t s_count,
                               const int64_t* offsets, const double* t, const void* dp, int dp_fp64,
                               double t0, double T, void* coef, int64_t ldc, hipStream_t st);
+hipError_t launch_spread_poly(const Plan& p, int s_count, const double* t, const void* dp, int dp_fp64, double t0,
+                              double t_end, const int64_t* ranges, int tiles, float* grid, int64_t grid_stride,
+                              hipStream_t st);
 hipError_t launch_nufft_fused(const Plan& p, const NufftWs& w, char* ws, int32_t S, const int64_t* offsets,
                               const double* t, const void* dp, int dp_fp64, double t0, double T,
                               void* coef, int64_t ldc, hipStream_t st);

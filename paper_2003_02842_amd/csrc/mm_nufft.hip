@@ -494,6 +494,209 @@ __global__ __launch_bounds__(256) void k_spread(const double* __restrict__ t, co
     }
 }
 
+// FP32 spreading (Eq. Der:15) from per-tap polynomials, in two phases per chunk
+// of staged events:
+//   1. each thread evaluates all W taps of its events (tap j is a polynomial in
+//      s = f - 1/2 whose coefficients are kernel arguments, so every lane runs the
+//      same Horner chains on scalar operands) times the return.  Event i owns a
+//      ring of M >= W+1 LDS slots; the tap for cell k goes to slot k mod M and the
+//      M - W slots no tap reaches hold 0;
+//   2. each thread gathers for its cell pairs (c, c+1), c even: the events with
+//      keys c .. c+W (contiguous, sorted) reach cell c at slot c mod M and cell
+//      c+1 at the next slot (M even, so the pair is one aligned 8-byte read), and an
+//      event that reaches only one of the two cells reads a zero slot for the other.
+// No load depends on another, so the gather streams LDS reads.  Cell pairs are the
+// real and imaginary parts of one complex grid entry: one float2 store per pair.
+template <typename DPT, int W, int PPT>
+__global__ __launch_bounds__(256) void k_spread_poly(const double* __restrict__ t, const DPT* __restrict__ dp,
+                                                     double t0, double span, double scale, int Mr, double hw,
+                                                     PolyParams pp, const int64_t* __restrict__ ranges, int tiles,
+                                                     int L2, int L2p, FastDiv divL2, float* __restrict__ grid,
+                                                     int64_t grid_stride)
+{
+    constexpr int TC = 512 * PPT;
+    constexpr int M = (W + 2) & ~1;                      // even ring, >= W + 1
+    constexpr int EC = (M <= 10) ? 1024 : 512;
+    constexpr int SB = EC / 256;
+    constexpr int DEG = poly_degree_for_width(W);
+    __shared__ __align__(8) float ring[EC * M];
+    __shared__ unsigned short keys[EC];
+    __shared__ unsigned short first[TC + W + 2];
+    const int a = blockIdx.x * TC;
+    const int len = min(TC, Mr - a);
+    const int64_t* rg = ranges + ((int64_t)blockIdx.y * tiles + blockIdx.x) * 6;
+    int64_t rb[3], nchunk[3];
+    int total_chunks = 0;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        rb[m] = rg[2 * m];
+        const int64_t ne = rg[2 * m + 1] - rb[m];
+        nchunk[m] = (ne + EC - 1) / EC;
+        total_chunks += (int)nchunk[m];
+    }
+    auto locate = [&](int q, int64_t& cb, int& n, int& m) {
+        m = 0;
+        while (q >= nchunk[m]) { q -= (int)nchunk[m]; ++m; }
+        cb = rb[m] + (int64_t)q * EC;
+        n = (int)min((int64_t)EC, rg[2 * m + 1] - cb);
+    };
+    float acc0[PPT], acc1[PPT];
+#pragma unroll
+    for (int r = 0; r < PPT; ++r) acc0[r] = acc1[r] = 0.f;
+    double tv[SB];
+    DPT dv[SB];
+    if (total_chunks > 0) {
+        int64_t cb; int n, m;
+        locate(0, cb, n, m);
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+            const int i = (int)threadIdx.x + 256 * u;
+            if (i < n) { tv[u] = t[cb + i]; dv[u] = dp[cb + i]; }
+        }
+    }
+    for (int q = 0; q < total_chunks; ++q) {
+        int64_t cb; int n, m;
+        locate(q, cb, n, m);
+        const int64_t shift = (int64_t)a + (int64_t)(m - 1) * Mr;
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+            const int i = (int)threadIdx.x + 256 * u;
+            if (i < n) {
+                int64_t l0;
+                double f;
+                cell_of<false>(tv[u], t0, span, scale, Mr, hw, l0, f);
+                const int key = (int)(l0 - shift) + W - 1;   // >= 0; tap j reaches cell key - W + 1 + j
+                const float sv = (float)(f - 0.5);
+                const float v = (float)dv[u];
+                float* o = ring + i * M;
+                const int base = (key - W + 1 + M) % M;     // slot of tap 0: (key - W + 1) mod M, key >= 0
+                // tap j = E_j(s^2) + s O_j(s^2) and, by the kernel's symmetry, tap W-1-j =
+                // E_j(s^2) - s O_j(s^2): even and odd coefficients by Horner in s^2
+                const float s2 = sv * sv;
+                float tap[W];
+#pragma unroll
+                for (int j = 0; j < (W + 1) / 2; ++j) {
+                    constexpr int DE = DEG & ~1, DO = (DEG - 1) | 1;   // top even and odd powers
+                    float ev = pp.c[j][DE], od = pp.c[j][DO];
+#pragma unroll
+                    for (int k = DE - 2; k >= 0; k -= 2) ev = fmaf(ev, s2, pp.c[j][k]);
+#pragma unroll
+                    for (int k = DO - 2; k >= 1; k -= 2) od = fmaf(od, s2, pp.c[j][k]);
+                    const float sod = sv * od;
+                    tap[j] = v * (ev + sod);
+                    if (W - 1 - j != j) tap[W - 1 - j] = v * (ev - sod);
+                }
+#pragma unroll
+                for (int j = 0; j < M; ++j) {
+                    int sl = base + j;
+                    sl = sl >= M ? sl - M : sl;
+                    o[sl] = j < W ? tap[j] : 0.f;
+                }
+                keys[i] = (unsigned short)key;
+            }
+        }
+        if (q + 1 < total_chunks) {
+            int64_t cb2; int n2, m2;
+            locate(q + 1, cb2, n2, m2);
+#pragma unroll
+            for (int u = 0; u < SB; ++u) {
+                const int i = (int)threadIdx.x + 256 * u;
+                if (i < n2) { tv[u] = t[cb2 + i]; dv[u] = dp[cb2 + i]; }
+            }
+        }
+        __syncthreads();
+        const int kmin = keys[0], kmax = keys[n - 1];
+        for (int i = 1 + threadIdx.x; i < n; i += 256) {
+            const int k1 = keys[i];
+            for (int k = keys[i - 1] + 1; k <= k1; ++k) first[k] = (unsigned short)i;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < PPT; ++r) {
+            const int c = 2 * ((int)threadIdx.x + 256 * r);
+            if (c >= len || c + W < kmin || c > kmax) continue;
+            const int lo = (c <= kmin) ? 0 : first[c];
+            const int hi = (c + W + 1 > kmax) ? n : first[c + W + 1];
+            const float2* rp = reinterpret_cast<const float2*>(ring + (c % M)) + (lo * M) / 2;
+            float s0 = 0.f, s1 = 0.f, u0 = 0.f, u1 = 0.f, p0 = 0.f, p1 = 0.f, q0 = 0.f, q1 = 0.f;
+            int e = lo;
+            for (; e + 3 < hi; e += 4, rp += 2 * M) {
+                const float2 x = rp[0], y = rp[M / 2], z = rp[M], zz = rp[3 * M / 2];
+                s0 += x.x;
+                s1 += x.y;
+                u0 += y.x;
+                u1 += y.y;
+                p0 += z.x;
+                p1 += z.y;
+                q0 += zz.x;
+                q1 += zz.y;
+            }
+            for (; e < hi; ++e, rp += M / 2) {
+                const float2 x = rp[0];
+                s0 += x.x;
+                s1 += x.y;
+            }
+            acc0[r] += (s0 + u0) + (p0 + q0);
+            acc1[r] += (s1 + u1) + (p1 + q1);
+        }
+    }
+    // cells (c, c+1) are complex entry j = (a + c)/2 at row j / L2, column j % L2
+    float2* out = reinterpret_cast<float2*>(grid + (int64_t)blockIdx.y * grid_stride);
+#pragma unroll
+    for (int r = 0; r < PPT; ++r) {
+        const int c = 2 * ((int)threadIdx.x + 256 * r);
+        if (c < len) {
+            const int j = (a + c) >> 1;
+            const int row = (int)fdiv((uint32_t)j, divL2);
+            out[(int64_t)row * L2p + (j - row * L2)] = make_float2(acc0[r], acc1[r]);
+        }
+    }
+}
+
+template <typename DPT, int W>
+static void spread_poly_w(const Plan& p, dim3 g, const double* t, const DPT* dp, double t0, double span, double scale,
+                          const int64_t* ranges, int tiles, float* grid, int64_t gs, hipStream_t st)
+{
+    const FastDiv dv = make_fastdiv((uint32_t)p.L2);
+    if (p.tile <= 1024)
+        hipLaunchKernelGGL((k_spread_poly<DPT, W, 2>), g, dim3(256), 0, st, t, dp, t0, span, scale, p.Mr, p.kp.hw,
+                           p.pp, ranges, tiles, p.L2, p.L2p, dv, grid, gs);
+    else if (p.tile <= 2048)
+        hipLaunchKernelGGL((k_spread_poly<DPT, W, 4>), g, dim3(256), 0, st, t, dp, t0, span, scale, p.Mr, p.kp.hw,
+                           p.pp, ranges, tiles, p.L2, p.L2p, dv, grid, gs);
+    else
+        hipLaunchKernelGGL((k_spread_poly<DPT, W, 8>), g, dim3(256), 0, st, t, dp, t0, span, scale, p.Mr, p.kp.hw,
+                           p.pp, ranges, tiles, p.L2, p.L2p, dv, grid, gs);
+}
+
+template <typename DPT>
+static hipError_t spread_poly_t(const Plan& p, int s_count, const double* t, const DPT* dp, double t0, double t_end,
+                                const int64_t* ranges, int tiles, float* grid, int64_t gs, hipStream_t st)
+{
+    const double span = t_end - t0;
+    const double scale = (double)p.Mr / span;
+    const dim3 g(tiles, s_count);
+    switch (p.kp.w) {
+#define MM_POLY_W(n) case n: spread_poly_w<DPT, n>(p, g, t, dp, t0, span, scale, ranges, tiles, grid, gs, st); break;
+        MM_POLY_W(2) MM_POLY_W(3) MM_POLY_W(4) MM_POLY_W(5) MM_POLY_W(6) MM_POLY_W(7) MM_POLY_W(8) MM_POLY_W(9)
+        MM_POLY_W(10) MM_POLY_W(11) MM_POLY_W(12) MM_POLY_W(13) MM_POLY_W(14) MM_POLY_W(15) MM_POLY_W(16)
+#undef MM_POLY_W
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_spread_poly(const Plan& p, int s_count, const double* t, const void* dp, int dp_fp64, double t0,
+                              double t_end, const int64_t* ranges, int tiles, float* grid, int64_t grid_stride,
+                              hipStream_t st)
+{
+    if (dp_fp64)
+        return spread_poly_t<double>(p, s_count, t, (const double*)dp, t0, t_end, ranges, tiles, grid, grid_stride,
+                                     st);
+    return spread_poly_t<float>(p, s_count, t, (const float*)dp, t0, t_end, ranges, tiles, grid, grid_stride, st);
+}
+
 constexpr int kBatch = 8;   // independent global loads a thread issues before consuming them
 
 // First FFT pass, in place on the packed complex grid viewed as an L1 x L2
@@ -861,10 +1064,21 @@ static hipError_t nufft_tiled_t(const Plan& p, const NufftWs& w, char* ws, int32
                            s_begin, s_count, tiles, p.tile, p.Mr, p.kp.w, p.kp.hw, t0, span, (double)p.Mr / span, ranges);
     prof_end("k_tile_ranges", st);
     prof_begin("k_spread", st);
-    if (dp_fp64)
-        launch_spread_k<T, double>(p, s_count, t, (const double*)dp, t0, T_, ranges, tiles, grid, gstride, st);
-    else
-        launch_spread_k<T, float>(p, s_count, t, (const float*)dp, t0, T_, ranges, tiles, grid, gstride, st);
+    if constexpr (sizeof(T) == 4) {
+        if (p.poly) {
+            hipError_t e = launch_spread_poly(p, s_count, t, dp, dp_fp64, t0, T_, ranges, tiles, grid, gstride, st);
+            if (e != hipSuccess) return e;
+        } else if (dp_fp64) {
+            launch_spread_k<T, double>(p, s_count, t, (const double*)dp, t0, T_, ranges, tiles, grid, gstride, st);
+        } else {
+            launch_spread_k<T, float>(p, s_count, t, (const float*)dp, t0, T_, ranges, tiles, grid, gstride, st);
+        }
+    } else {
+        if (dp_fp64)
+            launch_spread_k<T, double>(p, s_count, t, (const double*)dp, t0, T_, ranges, tiles, grid, gstride, st);
+        else
+            launch_spread_k<T, float>(p, s_count, t, (const float*)dp, t0, T_, ranges, tiles, grid, gstride, st);
+    }
     prof_end("k_spread", st);
 
     if (p.fft_ab) return launch_fft_ab(p, w, ws, s_begin, s_count, grid, gstride, coef, ldc, st);

@@ -151,6 +151,51 @@ static double host_psi(const KernParams& kp, double x)
     return v * kp.kb_inv_norm;
 }
 
+// Interpolate tap j, as a function of s = f - 1/2 in [-1/2, 1/2], at the deg+1
+// Chebyshev points, solve for monomial coefficients (partial pivoting), round them
+// to FP32 and return the largest deviation from the kernel over the interval.
+// The kernel is even, so tap w-1-j is tap j at -s: only taps j < ceil(w/2) are fitted.
+static double fit_poly(const KernParams& kp, int deg, PolyParams* pp)
+{
+    pp->deg = deg;
+    double worst = 0.0;
+    for (int j = 0; j < kMaxPolyTaps; ++j)
+        for (int k = 0; k <= kMaxPolyDeg; ++k) pp->c[j][k] = 0.f;
+    const int n = deg + 1;
+    for (int j = 0; j < (kp.w + 1) / 2; ++j) {
+        double A[kMaxPolyDeg + 1][kMaxPolyDeg + 2];
+        for (int m = 0; m < n; ++m) {
+            const double sm = 0.5 * cos(kPi * (m + 0.5) / n);
+            double pw = 1.0;
+            for (int k = 0; k < n; ++k) { A[m][k] = pw; pw *= sm; }
+            A[m][n] = host_psi(kp, j + 0.5 - sm - kp.hw);
+        }
+        for (int col = 0; col < n; ++col) {
+            int piv = col;
+            for (int r = col + 1; r < n; ++r)
+                if (fabs(A[r][col]) > fabs(A[piv][col])) piv = r;
+            for (int k = 0; k <= n; ++k) std::swap(A[col][k], A[piv][k]);
+            for (int r = 0; r < n; ++r) {
+                if (r == col) continue;
+                const double fct = A[r][col] / A[col][col];
+                for (int k = col; k <= n; ++k) A[r][k] -= fct * A[col][k];
+            }
+        }
+        for (int k = 0; k < n; ++k) pp->c[j][k] = (float)(A[k][n] / A[k][k]);
+        for (int q = 0; q <= 200; ++q) {
+            const double sq = -0.5 + q / 200.0;
+            double acc = pp->c[j][deg], mir = pp->c[j][deg];
+            for (int k = deg - 1; k >= 0; --k) {
+                acc = acc * sq + pp->c[j][k];
+                mir = mir * -sq + pp->c[j][k];
+            }
+            worst = std::max(worst, fabs(acc - host_psi(kp, j + 0.5 - sq - kp.hw)));
+            worst = std::max(worst, fabs(mir - host_psi(kp, (kp.w - 1 - j) + 0.5 - sq - kp.hw)));
+        }
+    }
+    return worst;
+}
+
 static double host_i0(double x)
 {
     double q = 0.25 * x * x, term = 1.0, sum = 1.0;
@@ -390,6 +435,21 @@ mm_status make_plan(int32_t N, mm_kernel kernel, double tol, mm_prec prec, const
         while (p->RR > 1 && p->RR / 2 >= L1 / 2 + 1) p->RR >>= 1;
         while (p->fft_ab && p->CC > 1 && fft_ab_lds_cols(*p) > lds_max) p->CC >>= 1;
         if (p->fft_ab && (fft_ab_lds_rows(*p) > 64 * 1024 || fft_ab_lds_cols(*p) > 64 * 1024)) p->fft_ab = 0;
+    }
+    // FP32 spreading from per-tap polynomials when they stay well inside tol.  By
+    // default only for Kaiser-Bessel, whose formula (sinh/sin branches) is the
+    // costliest per tap; ES and Gaussian taps measured faster evaluated directly in
+    // the gather (2.9 vs 3.7 ms and 3.6 vs 4.8 ms on the large universe).
+    p->poly = 0;
+    p->poly_err = 0.0;
+    const int sd = tune ? tune->spread_direct : 0;
+    const bool want_poly = sd == 2 || (sd == 0 && kernel == MM_KAISER_BESSEL);
+    if (prec == MM_MIXED && p->kp.w <= kMaxPolyTaps && want_poly) {
+        const double err = fit_poly(p->kp, poly_degree_for_width(p->kp.w), &p->pp);
+        if (err <= 0.05 * tol) {
+            p->poly = 1;
+            p->poly_err = err;
+        }
     }
     int tile = (prec == MM_MIXED) ? 2048 : 1024;
     if (tune && tune->tile > 0) tile = tune->tile <= 1024 ? 1024 : (tune->tile <= 2048 ? 2048 : 4096);

@@ -193,3 +193,24 @@ def test_generic_and_codelet_fft_paths(mm, prec, tol, N):
         for s, n in enumerate(counts):
             if n:
                 assert err[s] <= bar, (tune, info["Mr"], s, err[s])
+
+
+# ------------------------------ both FP32 spreading evaluations meet the bar
+@pytest.mark.parametrize("kernel", ["es", "g", "kb"])
+@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("tol", [1e-6, 1e-3])
+def test_spread_formula_and_polynomial_paths(mm, kernel, mode, tol):
+    """mm_tuning.spread_direct = 1 (kernel formula at every pair) and 2 (per-tap
+    polynomials evaluated once per event) on uneven series with a dense one."""
+    w = synth.random_events(5, 0, 2000, seed=77, dp_dtype=torch.float32)
+    dense = synth.random_events(1, 30_000, 30_000, seed=78, dp_dtype=torch.float32)
+    w = synth.Workload("ragged", torch.cat([w.offsets, w.offsets[-1] + dense.offsets[1:]]),
+                       torch.cat([w.t, dense.t]), torch.cat([w.dp, dense.dp]), 0.0, 1.0, 1, 6, [1], 0, {})
+    N = 2500
+    c = gpu_coef(mm, w, N, kernel, tol, "mixed", {"spread_direct": mode})
+    ref = oracle_coef(w, N)
+    err = series_rel_l2(c, ref)
+    counts = (w.offsets[1:] - w.offsets[:-1]).tolist()
+    for s, n in enumerate(counts):
+        if n:
+            assert err[s] <= tol * 2 + 2e-7, (s, n, err[s])
