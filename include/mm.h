@@ -217,6 +217,16 @@ mm_status mm_matrix_to_csr(int64_t n, int32_t D, const double* P, const double* 
                            double* t, void* dp, int32_t dp_is_fp64, int64_t cap, int32_t* nyq, void* ws,
                            size_t ws_bytes, mm_csr_info* info /* host */, void* stream);
 
+/* Negative control: the zero-padded FFT method (its algorithm in the appendix)
+ * puts every event on the nearest of Nstar equally spaced points of [t0, T)
+ * (index l = round(Nstar (t - t0)/(T - t0)), l = Nstar wrapping to 0), then takes
+ * an ordinary FFT.  This writes those moved times, out[i] = t0 + (T - t0) l/Nstar
+ * (device float64[E]; out may equal t), so that mm_nufft1 on them gives exactly
+ * what the zero-padded FFT computes (to tol).  On data already on such a grid (the
+ * missing-data representation) nothing moves; under arrival-time asynchrony the
+ * moves bias the estimate.  Asynchronous on `stream`.  Errors: MM_ERR_ARG, MM_ERR_HIP. */
+mm_status mm_snap_times(int64_t E, const double* t, double t0, double T, int64_t Nstar, double* out, void* stream);
+
 /* Human-readable text of a status (static storage). */
 const char* mm_status_string(mm_status s);
 

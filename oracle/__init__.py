@@ -155,3 +155,14 @@ def matrix_to_csr(P, T):
     t = np.concatenate(ts) if ts else np.zeros(0)
     dp = np.concatenate(dps) if dps else np.zeros(0)
     return np.array(offsets, dtype=np.int64), t, dp, np.array(nyq, dtype=np.int64), min(nyq), (t0, t1)
+
+
+def snap_times(t, t0: float, T: float, Nstar: int) -> np.ndarray:
+    """The zero-padded FFT method's grid assignment (appendix algorithm): each time
+    moves to the nearest of Nstar equally spaced points of [t0, T), the last
+    point wrapping to t0 (rounding half to even, like the C library's rint)."""
+    t = _np(t, np.float64)
+    span = T - t0
+    l = np.rint(((t - t0) / span) * float(Nstar)).astype(np.int64)
+    l[l >= Nstar] -= Nstar
+    return t0 + span * (l.astype(np.float64) / float(Nstar))

@@ -427,6 +427,13 @@ mm_status mm_matrix_to_csr(int64_t n, int32_t D, const double* P, const double* 
     return MM_OK;
 }
 
+mm_status mm_snap_times(int64_t E, const double* t, double t0, double T, int64_t Nstar, double* out, void* stream)
+{
+    if (E < 0 || Nstar < 1 || !isfinite(t0) || !isfinite(T) || !(T > t0)) return MM_ERR_ARG;
+    if (E > 0 && (!t || !out)) return MM_ERR_ARG;
+    return hip_status(launch_snap(E, t, t0, T, Nstar, out, (hipStream_t)stream));
+}
+
 mm_status mm_profile_enable(int32_t on)
 {
     std::lock_guard<std::mutex> lk(g_prof_mu);

@@ -231,6 +231,27 @@ __global__ void k_in_init(int D, double* mindt, int* flag)
     if (i == 0) *flag = 0;
 }
 
+// The zero-padded FFT method (appendix) moves every time to the nearest of Nstar
+// equally spaced points of [t0, T): l = round(u Nstar), u = (t - t0)/(T - t0),
+// l = Nstar wrapping to 0.
+__global__ void k_snap(int64_t E, const double* __restrict__ t, double t0, double span, int64_t Nstar,
+                       double* __restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= E) return;
+    const double u = __ddiv_rn(__dsub_rn(t[i], t0), span);
+    int64_t l = (int64_t)rint(__dmul_rn(u, (double)Nstar));
+    if (l >= Nstar) l -= Nstar;
+    out[i] = __dadd_rn(t0, __dmul_rn(span, __ddiv_rn((double)l, (double)Nstar)));
+}
+
+hipError_t launch_snap(int64_t E, const double* t, double t0, double T, int64_t Nstar, double* out, hipStream_t st)
+{
+    if (E == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_snap, dim3((unsigned)((E + 255) / 256)), dim3(256), 0, st, E, t, t0, T - t0, Nstar, out);
+    return hipGetLastError();
+}
+
 InputWs input_workspace(int64_t n, int32_t D)
 {
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };

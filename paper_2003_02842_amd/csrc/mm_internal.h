@@ -148,6 +148,7 @@ struct InputWs {
 InputWs input_workspace(int64_t n, int32_t D);
 hipError_t launch_input(int64_t n, int32_t D, const double* P, const double* Tm, int64_t ld, int64_t* offsets,
                         double* t, void* dp, int dp_fp64, int32_t* nyq, const InputWs& w, char* ws, hipStream_t st);
+hipError_t launch_snap(int64_t E, const double* t, double t0, double T, int64_t Nstar, double* out, hipStream_t st);
 hipError_t launch_input_returns(int32_t D, int64_t E, int64_t* offsets, double* t, void* dp, int dp_fp64,
                                 int32_t* nyq, const InputWs& w, char* ws, hipStream_t st);
 

@@ -28,7 +28,7 @@ _PRECS = {"fp64": PLAIN_FP64, "plain": PLAIN_FP64, "mixed": MIXED}
 
 EXPORTED = ["mm_plan_query", "mm_nufft1_workspace_size", "mm_nufft1", "mm_cov_workspace_size", "mm_cov",
             "mm_estimate_workspace_size", "mm_estimate", "mm_graph_cache_clear",
-            "mm_matrix_to_csr_workspace_size", "mm_matrix_to_csr",
+            "mm_matrix_to_csr_workspace_size", "mm_matrix_to_csr", "mm_snap_times",
             "mm_status_string", "mm_profile_enable", "mm_profile_read", "mm_profile_reset"]
 
 
@@ -75,6 +75,7 @@ def lib():
         L.mm_estimate.argtypes = [i32, i32, P, P, P, i32, f64, f64, P, i32, i32, i32, f64, i32, P, P, i64, P, P, P,
                                   sz, i32, P]
         L.mm_graph_cache_clear.argtypes = []
+        L.mm_snap_times.argtypes = [i64, P, f64, f64, i64, P, P]
         L.mm_matrix_to_csr_workspace_size.argtypes = [i64, i32, ctypes.POINTER(sz)]
         L.mm_matrix_to_csr.argtypes = [i64, i32, P, P, i64, P, P, P, i32, i64, P, P, sz, P, P]
         L.mm_status_string.argtypes = [i32]
@@ -325,3 +326,15 @@ def matrix_to_csr(P: torch.Tensor, T: torch.Tensor, dp_dtype=torch.float32, ws: 
     _check(st, "mm_matrix_to_csr")
     E = int(info.E)
     return offsets, t[:E], dp[:E], nyq, {"E": E, "N": int(info.N), "t0": info.t0, "T": info.T}
+
+
+def snap_times(t: torch.Tensor, t0: float, T: float, Nstar: int) -> torch.Tensor:
+    """Times moved to the nearest of Nstar equally spaced points of [t0, T)
+    (mm_snap_times): the zero-padded FFT method as a negative control."""
+    if not t.is_cuda or t.dtype != torch.float64:
+        raise TypeError("t must be a float64 device tensor")
+    t = t.contiguous()
+    out = torch.empty_like(t)
+    _check(lib().mm_snap_times(t.numel(), _ptr(t), float(t0), float(T), int(Nstar), _ptr(out), _stream()),
+           "mm_snap_times")
+    return out

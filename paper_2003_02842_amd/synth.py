@@ -277,6 +277,60 @@ def epps_replicates(G: int = 1000, D: int = 10, T_sec: float = 28_800.0, Nmax: i
                          true_corr=corr, rates=rates))
 
 
+def epps_pairs(G: int = 100, rho: float = 0.35, lam: float = 1 / 5, T_sec: float = 28_800.0,
+               seed: int = 20200311, dp_dtype=torch.float32, device="cpu") -> Workload:
+    """G replicates of a bivariate GBM (sigma^2 = (0.1, 0.2) daily, correlation
+    rho, mu = 0.01) on a 1 s grid over T_sec, both assets sampled by independent
+    Poisson arrivals of intensity lam per second (previous-tick prices): the
+    setting of the Epps-effect model, Eq. Der:21."""
+    g = _gen(seed, device)
+    sig2 = torch.tensor([0.1, 0.2], dtype=torch.float64)
+    corr = torch.tensor([[1.0, rho], [rho, 1.0]], dtype=torch.float64)
+    A = torch.linalg.cholesky(cov_from(sig2, corr)).to(device)
+    drift = (0.01 - 0.5 * sig2).to(device)
+    n_grid = int(T_sec)
+    h = 1.0 / SECONDS_PER_DAY
+    nmax = int(lam * T_sec + 10 * math.sqrt(lam * T_sec) + 32)
+    ts, ds, counts = [], [], []
+    for r in range(G):
+        Z = torch.randn(n_grid, 2, generator=g, dtype=torch.float64, device=device)
+        path = torch.cat([torch.zeros(1, 2, dtype=torch.float64, device=device),
+                          torch.cumsum(drift * h + math.sqrt(h) * (Z @ A.T), 0)])
+        e = torch.empty(2, nmax, dtype=torch.float64, device=device).exponential_(1.0, generator=g)
+        tau = torch.cumsum(e, 1) / lam
+        for i in range(2):
+            ti = tau[i][tau[i] < T_sec]
+            if ti.numel() == nmax:
+                raise RuntimeError("Poisson padding exhausted")
+            p = _previous_tick(path[:, i], 1.0, ti)
+            ts.append(ti[:-1])
+            ds.append(p[1:] - p[:-1])
+            counts.append(ti.numel() - 1)
+    offs = torch.zeros(2 * G + 1, dtype=torch.int64)
+    offs[1:] = torch.cumsum(torch.tensor(counts, dtype=torch.int64), 0)
+    return Workload("epps-pairs", offs.to(device), torch.cat(ts), torch.cat(ds).to(dp_dtype), 0.0, T_sec, G, 2,
+                    [1], seed, dict(rho=rho, lam=lam))
+
+
+def missing_data(n: int = 10_000, keep: float = 0.6, seed: int = 20200312, dp_dtype=torch.float64) -> Workload:
+    """The missing-data representation: the bivariate synchronous GBM on n equally
+    spaced times over one day with each asset keeping a random fraction ``keep``
+    of its observations (the paper down-samples by 40%); returns span the gaps."""
+    w = bivariate_sync(n=n, seed=seed, dp_dtype=torch.float64)
+    g = _gen(seed + 1, "cpu")
+    series = []
+    for s in range(2):
+        tt, dd = w.series(s)
+        logp = torch.cat([torch.zeros(1, dtype=torch.float64), torch.cumsum(dd, 0)])   # n observations
+        times = torch.cat([tt, tt[-1:] + w.T / n])                                      # all n observation times
+        mask = torch.rand(times.numel(), generator=g) < keep
+        mask[0] = True
+        mask[-1] = True
+        tk, lk = times[mask], logp[mask]
+        series.append((tk[:-1], lk[1:] - lk[:-1]))
+    return _pack("missing-data", series, w.t0, w.T, 1, 2, [w.Ns[0]], seed, dp_dtype, dict(keep=keep))
+
+
 def large_universe(D: int = 2000, n_lo: float = 1e4, n_hi: float = 1e6, N: int = 50_000,
                    T_sec: float = 28_800.0, n_factors: int = 3, factor_grid: float = 1e-3,
                    seed: int = 20200310, dp_dtype=torch.float32, device="cpu") -> Workload:

@@ -1,0 +1,120 @@
+"""Autotuner of the mixed-precision NUFFT plan: oversampling factor sigma,
+spreading tile (cells per workgroup) and the FP32 spreading evaluation (kernel
+formula per pair or per-tap polynomials), timed on the caller's own data.
+
+For each sigma the planner already picks the smallest kernel width whose
+a-priori error estimate meets tol (the width follows from sigma and tol), so the
+search space is sigma x tile x evaluation.  A candidate is admitted only if, on
+a calibration subset of the series, the covariance built from its coefficients
+stays within ``sigma_tol`` (relative Frobenius) of the FP64 form at tol 1e-12;
+the fastest admitted candidate wins.  Results can be cached in a JSON file keyed
+by the device, the workload shape and the request.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+import torch
+
+from paper_2003_02842_amd import mm
+
+SIGMAS = (1.5, 1.75, 2.0, 2.25, 2.5)
+TILES = (1024, 2048, 4096)
+EVALS = (1, 2)   # mm_tuning.spread_direct: 1 kernel formula per pair, 2 per-tap polynomials
+
+
+def _key(S, E, N, kernel, tol, basis):
+    dev = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "none"
+    # events bucketed by powers of two: the tuning transfers between similar sizes
+    return "%s|S=%d|E~2^%d|N=%d|%s|tol=%g|%s" % (dev, S, max(E, 1).bit_length(), N, kernel, tol, basis)
+
+
+def _time_ms(fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    best = float("inf")
+    for _ in range(reps):
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        best = min(best, a.elapsed_time(b))
+    return best
+
+
+def autotune(offsets, t, dp, t0: float, T: float, N: int, kernel="es", tol: float = 1e-6, basis="fejer",
+             sigma_tol: float = 1e-5, calib_series: int = 16, sigmas=SIGMAS, tiles=TILES, evals=EVALS,
+             reps: int = 3, cache_path: str = None, verbose: bool = False) -> dict:
+    """Fastest admitted mm_tuning (as a dict with the chosen plan) for
+    mm_nufft1(offsets, t, dp, t0, T, N, kernel, tol, "mixed").
+
+    The calibration subset is the ``calib_series`` series with the most events
+    (the hardest for the FP32 sums); its FP64 reference uses the same kernel at
+    tol 1e-12."""
+    S = offsets.numel() - 1
+    E = int(offsets[-1])
+    key = _key(S, E, N, kernel, tol, basis)
+    if cache_path and os.path.exists(cache_path):
+        with open(cache_path) as fh:
+            cache = json.load(fh)
+        if key in cache:
+            return dict(cache[key], cached=True)
+    counts = (offsets[1:] - offsets[:-1]).cpu()
+    pick = torch.argsort(counts, descending=True)[:min(calib_series, S)].sort().values.tolist()
+    # calibration subset as its own CSR workload
+    offs_c, ts, ds = [0], [], []
+    for s in pick:
+        a, b = int(offsets[s]), int(offsets[s + 1])
+        ts.append(t[a:b])
+        ds.append(dp[a:b])
+        offs_c.append(offs_c[-1] + (b - a))
+    oc = torch.tensor(offs_c, dtype=torch.int64, device=t.device)
+    tc, dc = torch.cat(ts), torch.cat(ds)
+    D = len(pick)
+    c64 = mm.nufft1(oc, tc, dc.to(torch.float64), t0, T, N, kernel, 1e-12, "fp64")
+    S_ref, _ = mm.cov(c64, 1, D, [N], basis, correlation=False)
+    S_ref = S_ref.double()
+    results = []
+    out = torch.empty((S, N + 1), dtype=torch.complex64, device=t.device)
+    for sg in sigmas:
+        for ev in evals:
+            base = {"sigma": float(sg), "spread_direct": int(ev)}
+            try:
+                plan = mm.plan_query(N, kernel, tol, "mixed", base)
+            except mm.MMError:
+                continue
+            cc = mm.nufft1(oc, tc, dc, t0, T, N, kernel, tol, "mixed", base)
+            Sm, _ = mm.cov(cc, 1, D, [N], basis, correlation=False)
+            err = float(torch.linalg.norm((Sm.double() - S_ref).flatten()) / torch.linalg.norm(S_ref.flatten()))
+            if not err <= sigma_tol:
+                if verbose:
+                    print("tune: sigma %.2f eval %d rejected (err %.2e)" % (sg, ev, err))
+                continue
+            for tile in tiles:
+                tune = dict(base, tile=int(tile))
+                ws = torch.empty(mm.nufft1_workspace_size(S, N, kernel, tol, "mixed", tune), dtype=torch.uint8,
+                                 device=t.device)
+                ms = _time_ms(lambda: mm.nufft1(offsets, t, dp, t0, T, N, kernel, tol, "mixed", tune, out=out, ws=ws),
+                              reps)
+                del ws
+                results.append((ms, tune, plan, err))
+                if verbose:
+                    print("tune: %s width %d Mr %d: %.3f ms (err %.2e)" % (tune, plan["width"], plan["Mr"], ms, err))
+    if not results:
+        raise RuntimeError("no candidate met the accuracy target")
+    ms, tune, plan, err = min(results, key=lambda r: r[0])
+    best = {"tuning": tune, "ms": ms, "width": plan["width"], "Mr": plan["Mr"], "calib_err": err,
+            "candidates": len(results)}
+    if cache_path:
+        cache = {}
+        if os.path.exists(cache_path):
+            with open(cache_path) as fh:
+                cache = json.load(fh)
+        cache[key] = best
+        tmp = cache_path + ".tmp"
+        with open(tmp, "w") as fh:
+            json.dump(cache, fh, indent=1, sort_keys=True)
+        os.replace(tmp, cache_path)
+    return dict(best, cached=False)

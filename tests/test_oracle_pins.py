@@ -296,3 +296,33 @@ def test_matrix_input_round_trip_of_csr_workload():
     assert off.tolist() == w.offsets.tolist()
     np.testing.assert_array_equal(t, w.t.numpy())
     np.testing.assert_allclose(dp, w.dp.double().numpy(), atol=1e-12)
+
+
+# --------------------------------------- zero-padded FFT grid and Epps helpers
+def test_snap_times_grid_points_and_wrap():
+    """Grid points stay, half-way times round to even, u -> 1 wraps to t0 (the
+    zero-padded FFT's assignment to the nearest of Nstar points of [t0, T))."""
+    t = np.array([0.0, 0.25, 0.5, 0.125, 0.375, 0.99, 1.0])
+    got = oracle.snap_times(t, 0.0, 1.0, 4)
+    np.testing.assert_array_equal(got, [0.0, 0.25, 0.5, 0.0, 0.5, 0.0, 0.0])
+
+
+def test_epps_cutoff_conversion():
+    from paper_2003_02842_amd import epps
+    for N in (1, 7, 14399, 50000):
+        T = 2.0 * N + 1.0
+        assert epps.cutoff_for_interval(T, epps.interval_for_cutoff(T, N)) == N
+    assert epps.cutoff_for_interval(28_800.0, 1.0) == 14_399           # Eq. Der:22
+    assert epps.cutoff_for_interval(28_800.0, 100.0) == 143
+
+
+def test_epps_model_limits_and_fit():
+    from paper_2003_02842_amd import epps
+    assert abs(epps.epps_model(1e6, 0.6, 1.0) - 0.6) < 1e-6             # long intervals: the full correlation
+    assert epps.epps_model(1e-6, 0.6, 1.0) < 1e-5                        # short intervals: decorrelated
+    dt = np.array([1, 2, 3, 5, 8, 13, 21, 34, 55, 89], float)
+    rho = epps.epps_model(dt, 0.621, 1 / 13.5)
+    c, lam, rss = epps.fit_epps(dt, rho)
+    assert abs(c - 0.621) < 1e-6 and abs(lam - 1 / 13.5) < 1e-6 and rss < 1e-20
+    c2, lam2, _ = epps.fit_epps(dt, rho, lam=1 / 13.5)
+    assert abs(c2 - 0.621) < 1e-12 and lam2 == 1 / 13.5
