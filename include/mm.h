@@ -184,6 +184,27 @@ mm_status mm_estimate(int32_t G, int32_t D, const int64_t* offsets, const double
 /* Synchronises the device and frees every graph mm_estimate recorded. */
 mm_status mm_graph_cache_clear(void);
 
+/* Bytes of device workspace mm_cov_pairwise needs (Ni: host int32[D]). */
+mm_status mm_cov_pairwise_workspace_size(int32_t G, int32_t D, const int32_t* Ni, mm_prec prec,
+                                         size_t* bytes /* host */);
+
+/* Pairwise estimates with per-asset cutoffs (Sec. 3: when assets have their own
+ * Nyquist cutoffs N_i, pair (i, j) is estimated at N_ij = min(N_i, N_j)):
+ *   cov[g][i][j]  = the Dirichlet or Fejer estimate of pair (i, j) at N_ij
+ *   corr[g][i][j] = cov_ij(N_ij) / sqrt(cov_ii(N_ij) cov_jj(N_ij)), the correlation of the
+ *                  pairwise 2 x 2 estimate (NaN for a non-positive variance); may be NULL
+ * The diagonal holds each asset's variance at its own N_i.  One coefficient set
+ * (columns 0..max N_i) serves all pairs: the estimate is swept over the distinct
+ * cutoffs (at most 128) and each entry read from its pair's cutoff.
+ *   coef   (G*D) x ldc as for mm_cov, ldc >= max N_i + 1
+ *   Ni     host int32[D], each >= 1, shared by all groups
+ *   cov, corr  G x D x D, float (MM_MIXED) or double (MM_PLAIN_FP64)
+ * Synchronises `stream`.  The result need not be positive semi-definite.
+ * Errors: MM_ERR_ARG, MM_ERR_WORKSPACE, MM_ERR_UNSUPPORTED (more than 128 distinct cutoffs),
+ * MM_ERR_HIP. */
+mm_status mm_cov_pairwise(int32_t G, int32_t D, const void* coef, int64_t ldc, const int32_t* Ni, mm_basis basis,
+                          mm_prec prec, void* cov, void* corr, void* ws, size_t ws_bytes, void* stream);
+
 /* Result of mm_matrix_to_csr (host). */
 typedef struct {
     int64_t E;                 /* returns written (CSR length) */

@@ -166,3 +166,20 @@ def snap_times(t, t0: float, T: float, Nstar: int) -> np.ndarray:
     l = np.rint(((t - t0) / span) * float(Nstar)).astype(np.int64)
     l[l >= Nstar] -= Nstar
     return t0 + span * (l.astype(np.float64) / float(Nstar))
+
+
+def cov_pairwise(coef: np.ndarray, G: int, D: int, Ni, basis: int):
+    """Pairwise estimates (Sec. 3): entry (i, j) is the 2 x 2 estimate of the pair
+    at N_ij = min(N_i, N_j); R_ij from that 2 x 2 estimate.  Shapes (G, D, D)."""
+    Ni = [int(n) for n in Ni]
+    cov_out = np.zeros((G, D, D))
+    corr_out = np.zeros((G, D, D))
+    for g in range(G):
+        for i in range(D):
+            for j in range(D):
+                N = min(Ni[i], Ni[j])
+                rows = np.ascontiguousarray(coef[[g * D + i, g * D + j], :N + 1])
+                S2, R2 = cov(rows, 1, 2, [N], basis)
+                cov_out[g, i, j] = S2[0, 0, 0, 1] if i != j else S2[0, 0, 0, 0]
+                corr_out[g, i, j] = R2[0, 0, 0, 1] if i != j else R2[0, 0, 0, 0]
+    return cov_out, corr_out

@@ -427,6 +427,65 @@ mm_status mm_matrix_to_csr(int64_t n, int32_t D, const double* P, const double* 
     return MM_OK;
 }
 
+// Distinct ascending cutoffs of Ni and each asset's slot among them.
+static bool pairwise_cutoffs(int32_t D, const int32_t* Ni, std::vector<int32_t>& Ns, std::vector<int32_t>& slot)
+{
+    Ns.assign(Ni, Ni + D);
+    std::sort(Ns.begin(), Ns.end());
+    Ns.erase(std::unique(Ns.begin(), Ns.end()), Ns.end());
+    if (Ns.empty() || Ns.front() < 1 || (int)Ns.size() > kMaxCutoffs) return false;
+    slot.resize(D);
+    for (int i = 0; i < D; ++i) slot[i] = (int32_t)(std::lower_bound(Ns.begin(), Ns.end(), Ni[i]) - Ns.begin());
+    return true;
+}
+
+static size_t pairwise_layout(int32_t G, int32_t D, int32_t Nmax, int32_t nq, mm_prec prec, size_t* sweep_off,
+                              size_t* cov_off)
+{
+    const size_t es = prec == MM_MIXED ? 4 : 8;
+    size_t cw = 0;
+    mm_cov_workspace_size(G, D, Nmax, nq, prec, &cw);
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    *sweep_off = al(4 * (size_t)D);
+    *cov_off = *sweep_off + al((size_t)nq * G * D * D * es);
+    return *cov_off + al(cw);
+}
+
+mm_status mm_cov_pairwise_workspace_size(int32_t G, int32_t D, const int32_t* Ni, mm_prec prec, size_t* bytes)
+{
+    if (!bytes || !Ni || G < 1 || D < 1 || (prec != MM_PLAIN_FP64 && prec != MM_MIXED)) return MM_ERR_ARG;
+    std::vector<int32_t> Ns, slot;
+    if (!pairwise_cutoffs(D, Ni, Ns, slot)) return (Ns.size() > (size_t)kMaxCutoffs) ? MM_ERR_UNSUPPORTED : MM_ERR_ARG;
+    size_t a, b;
+    *bytes = pairwise_layout(G, D, Ns.back(), (int32_t)Ns.size(), prec, &a, &b);
+    return MM_OK;
+}
+
+mm_status mm_cov_pairwise(int32_t G, int32_t D, const void* coef, int64_t ldc, const int32_t* Ni, mm_basis basis,
+                          mm_prec prec, void* cov, void* corr, void* ws, size_t ws_bytes, void* stream)
+{
+    if (G < 1 || D < 1 || !coef || !cov || !Ni) return MM_ERR_ARG;
+    if (basis != MM_DIRICHLET && basis != MM_FEJER) return MM_ERR_ARG;
+    if (prec != MM_PLAIN_FP64 && prec != MM_MIXED) return MM_ERR_ARG;
+    std::vector<int32_t> Ns, slot;
+    if (!pairwise_cutoffs(D, Ni, Ns, slot)) return (Ns.size() > (size_t)kMaxCutoffs) ? MM_ERR_UNSUPPORTED : MM_ERR_ARG;
+    const int32_t nq = (int32_t)Ns.size(), Nmax = Ns.back();
+    if ((int64_t)Nmax > ldc - 1) return MM_ERR_ARG;
+    if (small_d_limit(D) && G > 65535) return MM_ERR_UNSUPPORTED;
+    size_t sweep_off, cov_off;
+    const size_t need = pairwise_layout(G, D, Nmax, nq, prec, &sweep_off, &cov_off);
+    if (!ws || ws_bytes < need) return MM_ERR_WORKSPACE;
+    if (((uintptr_t)ws & 255) != 0) return MM_ERR_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    char* wsb = (char*)ws;
+    if (hipMemcpyAsync(wsb, slot.data(), 4 * (size_t)D, hipMemcpyHostToDevice, st) != hipSuccess) return MM_ERR_HIP;
+    hipError_t e = enqueue_cov(G, D, coef, ldc, Ns.data(), nq, Nmax, basis, prec, wsb + sweep_off, nullptr,
+                               wsb + cov_off, st);
+    if (e == hipSuccess) e = launch_pairwise_select(prec, G, D, (const int32_t*)wsb, wsb + sweep_off, cov, corr, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);   // the host slot table must outlive the copy
+    return hip_status(e);
+}
+
 mm_status mm_snap_times(int64_t E, const double* t, double t0, double T, int64_t Nstar, double* out, void* stream)
 {
     if (E < 0 || Nstar < 1 || !isfinite(t0) || !isfinite(T) || !(T > t0)) return MM_ERR_ARG;

@@ -479,6 +479,43 @@ __global__ __launch_bounds__(256) void k_syrk_reduce(const float* __restrict__ p
     }
 }
 
+// Pairwise cutoffs: entry (i, j) of group g from the sweep slice of cutoff
+// N_ij = min(N_i, N_j), and R_ij from the same slice's variances.
+template <typename OT>
+__global__ void k_pairwise_select(int64_t total, int D, int G, const int32_t* __restrict__ qidx,
+                                  const OT* __restrict__ sweep, OT* __restrict__ cov, OT* __restrict__ corr)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    const int64_t DD = (int64_t)D * D;
+    const int64_t g = idx / DD;
+    const int r = (int)(idx - g * DD);
+    const int i = r / D, j = r - i * D;
+    const int qi = qidx[i], qj = qidx[j];
+    const int q = qi < qj ? qi : qj;     // slices ascend with the cutoff
+    const OT* Sq = sweep + ((int64_t)q * G + g) * DD;
+    const OT v = Sq[r];
+    cov[idx] = v;
+    if (corr) {
+        const OT a = Sq[(int64_t)i * D + i], b = Sq[(int64_t)j * D + j];
+        corr[idx] = (a > (OT)0 && b > (OT)0) ? v / (sqrt(a) * sqrt(b)) : (OT)NAN;
+    }
+}
+
+hipError_t launch_pairwise_select(int prec, int32_t G, int32_t D, const int32_t* qidx, const void* sweep, void* cov,
+                                  void* corr, hipStream_t st)
+{
+    const int64_t total = (int64_t)G * D * D;
+    const int blocks = (int)((total + 255) / 256);
+    if (prec == MM_MIXED)
+        hipLaunchKernelGGL(k_pairwise_select<float>, dim3(blocks), dim3(256), 0, st, total, D, G, qidx,
+                           (const float*)sweep, (float*)cov, (float*)corr);
+    else
+        hipLaunchKernelGGL(k_pairwise_select<double>, dim3(blocks), dim3(256), 0, st, total, D, G, qidx,
+                           (const double*)sweep, (double*)cov, (double*)corr);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------------------- launchers
 static SortedCutoffs sort_cutoffs(const Cutoffs& c)
 {

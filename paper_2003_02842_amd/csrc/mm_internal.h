@@ -161,6 +161,8 @@ hipError_t launch_cov_small(int prec, int32_t G, int32_t D, const void* coef, in
                             const Cutoffs& cut, int basis, void* cov, hipStream_t st);
 hipError_t launch_corr(int prec, int64_t mats, int32_t D, const void* cov, void* corr, hipStream_t st);
 size_t cov_mfma_workspace(int32_t G, int32_t D, int32_t Nmax);
+hipError_t launch_pairwise_select(int prec, int32_t G, int32_t D, const int32_t* qidx, const void* sweep, void* cov,
+                                  void* corr, hipStream_t st);
 hipError_t launch_cov_mfma(int32_t G, int32_t D, const void* coef, int64_t ldc, int32_t N, int basis,
                            void* cov, char* ws, hipStream_t st);
 hipError_t launch_cov_fp64(int32_t G, int32_t D, const void* coef, int64_t ldc, int32_t N, int basis,

@@ -29,6 +29,7 @@ _PRECS = {"fp64": PLAIN_FP64, "plain": PLAIN_FP64, "mixed": MIXED}
 EXPORTED = ["mm_plan_query", "mm_nufft1_workspace_size", "mm_nufft1", "mm_cov_workspace_size", "mm_cov",
             "mm_estimate_workspace_size", "mm_estimate", "mm_graph_cache_clear",
             "mm_matrix_to_csr_workspace_size", "mm_matrix_to_csr", "mm_snap_times",
+            "mm_cov_pairwise_workspace_size", "mm_cov_pairwise",
             "mm_status_string", "mm_profile_enable", "mm_profile_read", "mm_profile_reset"]
 
 
@@ -76,6 +77,8 @@ def lib():
                                   sz, i32, P]
         L.mm_graph_cache_clear.argtypes = []
         L.mm_snap_times.argtypes = [i64, P, f64, f64, i64, P, P]
+        L.mm_cov_pairwise_workspace_size.argtypes = [i32, i32, P, i32, ctypes.POINTER(sz)]
+        L.mm_cov_pairwise.argtypes = [i32, i32, P, i64, P, i32, i32, P, P, P, sz, P]
         L.mm_matrix_to_csr_workspace_size.argtypes = [i64, i32, ctypes.POINTER(sz)]
         L.mm_matrix_to_csr.argtypes = [i64, i32, P, P, i64, P, P, P, i32, i64, P, P, sz, P, P]
         L.mm_status_string.argtypes = [i32]
@@ -338,3 +341,31 @@ def snap_times(t: torch.Tensor, t0: float, T: float, Nstar: int) -> torch.Tensor
     _check(lib().mm_snap_times(t.numel(), _ptr(t), float(t0), float(T), int(Nstar), _ptr(out), _stream()),
            "mm_snap_times")
     return out
+
+
+def cov_pairwise(coef: torch.Tensor, G: int, D: int, Ni, basis="dirichlet", correlation: bool = True,
+                 ws: torch.Tensor = None):
+    """Pairwise estimates at N_ij = min(N_i, N_j) (mm_cov_pairwise): (G, D, D)
+    covariance and correlation."""
+    if coef.dtype == torch.complex64:
+        p, rdt = MIXED, torch.float32
+    elif coef.dtype == torch.complex128:
+        p, rdt = PLAIN_FP64, torch.float64
+    else:
+        raise TypeError("coef must be complex64 (mixed) or complex128 (fp64)")
+    if not coef.is_cuda or coef.dim() != 2 or coef.stride(1) != 1 or coef.shape[0] != G * D:
+        raise ValueError("coef must be a (G*D, ldc) device tensor with unit column stride")
+    Ni = [int(n) for n in Ni]
+    if len(Ni) != D:
+        raise ValueError("Ni must hold one cutoff per asset")
+    arr = (ctypes.c_int32 * D)(*Ni)
+    need = ctypes.c_size_t(0)
+    _check(lib().mm_cov_pairwise_workspace_size(int(G), int(D), arr, p, ctypes.byref(need)),
+           "mm_cov_pairwise_workspace_size")
+    if ws is None or ws.numel() < need.value:
+        ws = _workspace(need.value, coef.device)
+    covt = torch.empty((G, D, D), dtype=rdt, device=coef.device)
+    corrt = torch.empty_like(covt) if correlation else None
+    _check(lib().mm_cov_pairwise(int(G), int(D), _ptr(coef), coef.stride(0), arr, _enum(basis, _BASES, "basis"), p,
+                                 _ptr(covt), _ptr(corrt), _ptr(ws), ws.numel(), _stream()), "mm_cov_pairwise")
+    return covt, corrt

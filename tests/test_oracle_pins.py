@@ -326,3 +326,29 @@ def test_epps_model_limits_and_fit():
     assert abs(c - 0.621) < 1e-6 and abs(lam - 1 / 13.5) < 1e-6 and rss < 1e-20
     c2, lam2, _ = epps.fit_epps(dt, rho, lam=1 / 13.5)
     assert abs(c2 - 0.621) < 1e-12 and lam2 == 1 / 13.5
+
+
+# ------------------------------------------------------------ pairwise cutoffs
+def test_pairwise_equal_cutoffs_is_the_ordinary_estimate():
+    w = synth.random_events(4, 20, 200, seed=9)
+    N = 40
+    c = oracle.coeffs_batch(w.offsets, w.t, w.dp, w.t0, w.T, N)
+    for basis in (oracle.DIRICHLET, oracle.FEJER):
+        S, R = oracle.cov(c, 1, 4, [N], basis)
+        Sp, Rp = oracle.cov_pairwise(c, 1, 4, [N] * 4, basis)
+        np.testing.assert_allclose(Sp[0], S[0, 0], rtol=1e-14, atol=0)
+        np.testing.assert_allclose(Rp[0], R[0, 0], rtol=1e-14, atol=0)
+
+
+def test_pairwise_single_jumps_closed_form():
+    """Two assets with one jump each at the same time: the Fejer variance of asset
+    i is delta_i^2 N_i/(N_i + 1) at its own cutoff, the covariance
+    delta_1 delta_2 N/(N+1) at N = min(N_1, N_2), and the correlation 1."""
+    t = torch.tensor([0.3, 0.3], dtype=torch.float64)
+    dp = torch.tensor([0.5, -0.2], dtype=torch.float64)
+    offs = torch.tensor([0, 1, 2])
+    Ni = [7, 30]
+    c = oracle.coeffs_batch(offs, t, dp, 0.0, 1.0, max(Ni))
+    S, R = oracle.cov_pairwise(c, 1, 2, Ni, oracle.FEJER)
+    assert abs(S[0, 0, 0] - 0.25 * 7 / 8) < 1e-15 and abs(S[0, 1, 1] - 0.04 * 30 / 31) < 1e-15
+    assert abs(S[0, 0, 1] - (-0.1) * 7 / 8) < 1e-15 and abs(R[0, 0, 1] + 1.0) < 1e-14
