@@ -21,9 +21,12 @@
 
 #include "mm_internal.h"
 
-// Events staged per LDS chunk by the FP32 spreading kernel (a multiple of 256).
+// Events staged per LDS chunk by the FP32 spreading kernels (multiples of 512).
 #ifndef MM_SPREAD_CHUNK
 #define MM_SPREAD_CHUNK 2048
+#endif
+#ifndef MM_POLY_CHUNK
+#define MM_POLY_CHUNK 512
 #endif
 
 namespace mm {
@@ -516,7 +519,7 @@ __global__ __launch_bounds__(256) void k_spread_poly(const double* __restrict__ 
 {
     constexpr int TC = 512 * PPT;
     constexpr int M = (W + 2) & ~1;                      // even ring, >= W + 1
-    constexpr int EC = (M <= 10) ? 1024 : 512;
+    constexpr int EC = (M <= 12) ? MM_POLY_CHUNK : MM_POLY_CHUNK / 2;   // ~25 KB of LDS: 6 workgroups per CU
     constexpr int SB = EC / 256;
     constexpr int DEG = poly_degree_for_width(W);
     __shared__ __align__(8) float ring[EC * M];
