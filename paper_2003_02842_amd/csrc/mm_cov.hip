@@ -7,12 +7,14 @@
 // s_k = 2pi sqrt(m_k w_k), with itself.
 //
 //   k_cov_small     small D, any number of cutoffs: one workgroup per group of
-//                   series, one thread per (i, j) pair, running FP64 prefix sums
+//                   series, a power of two of lanes per (i, j) pair, FP64 running sums
 //                   S0(N) = sum m_k P_k and S1(N) = sum m_k k P_k over k, read off
 //                   at every cutoff (Dirichlet S0/(2N+1), Fejer (S0 - S1/N)/(N+1))
 //   k_split_bf16    X in BF16 hi/lo parts: hi = rne(x), lo = rne(x - hi)
-//   k_syrk_mfma     lower-triangle 128x128 tiles of X X^T on v_mfma_f32_32x32x16_bf16,
-//                   hi*hi + hi*lo + lo*hi with FP32 accumulation, split over k
+//   k_syrk_mfma256  lower-triangle 256x256 tiles of X X^T on v_mfma_f32_32x32x16_bf16,
+//                   hi*hi + hi*lo + lo*hi with FP32 accumulation, split over k; operand
+//                   tiles go HBM -> LDS by global_load_lds, double-buffered
+//   k_syrk_mfma     the same on 128x128 tiles (smaller D)
 //   k_syrk_reduce   sum of the k-splits, mirrored to the full matrix
 //   k_cov_fp64      FP64 tiled product for the plain form
 //   k_corr          R_ij = Sigma_ij / sqrt(Sigma_ii Sigma_jj), NaN if a variance <= 0
