@@ -140,13 +140,17 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     mm.profile_enable(False)
-    names = ["k_prep", "k_tile_ranges", "k_spread", "k_fft_cols", "k_fft_rows", "k_split_bf16", "k_syrk_mfma", "k_syrk_reduce",
-             "k_corr", "k_cov_small"]
+    # kernel names as launched (the planner picks one kernel per role)
+    roles = {"spread": ("k_spread_poly", "k_spread"), "fft_cols": ("k_fft_cols_ab", "k_fft_cols"),
+             "fft_rows": ("k_fft_rows_ab", "k_fft_rows"), "syrk": ("k_syrk_mfma256", "k_syrk_mfma")}
+    names = ["k_prep", "k_tile_ranges", "k_split_bf16", "k_syrk_reduce", "k_corr", "k_cov_small"] + \
+        [n for r in roles.values() for n in r]
     kern = {}
     for nm in names:
         ms, n = mm.profile_read(nm)
         if n:
             kern[nm] = {"avg_ms": ms / n, "launches": n}
+    role = {r: next((n for n in cands if n in kern), None) for r, cands in roles.items()}
     ms_step = 1e3 * elapsed / a.steps
     print("# mixed: %.3f ms/step  %s" % (ms_step, json.dumps({k: round(v["avg_ms"], 4) for k, v in kern.items()})),
           file=sys.stderr, flush=True)
@@ -154,24 +158,25 @@ def main():
     # contraction throughput (GEMM-equivalent flops)
     K = 2 * N + 1
     gemm_flops = 2.0 * D * D * K
-    t_con = sum(kern.get(k, {"avg_ms": 0})["avg_ms"] for k in ("k_split_bf16", "k_syrk_mfma", "k_syrk_reduce"))
+    t_con = sum(kern[k]["avg_ms"] for k in ("k_split_bf16", role["syrk"], "k_syrk_reduce") if k in kern)
     con_tflops = gemm_flops / (t_con * 1e-3) / 1e12 if t_con > 0 else None
 
-    # roofline of the dominant kernel
+    # roofline of the dominant kernel: algorithmic bytes (flops) per launch over the
+    # mean launch duration from HIP events on the launch stream
     dom = max(kern, key=lambda k: kern[k]["avg_ms"])
     default_workload = (a.D, a.n_lo, a.n_hi, a.N, a.kernel, a.tol, a.basis, a.seed, a.width) == \
         (2000, 1e4, 1e6, 50_000, "es", 1e-6, "fejer", 20200310, 0)
     traffic = measured_traffic(dom) if default_workload else None
     Mr = plan["Mr"]
     alg_bytes = {
-        "k_spread": E * (8 + 4) + S * Mr * 4 + (S + 1) * 8,
-        "k_fft_cols": 2 * S * (Mr // 2) * 8,
-        "k_fft_rows": S * (Mr // 2) * 8 + S * (N + 1) * 8,
+        role["spread"]: E * (8 + 4) + S * Mr * 4 + (S + 1) * 8,
+        role["fft_cols"]: 2 * S * (Mr // 2) * 8,
+        role["fft_rows"]: S * (Mr // 2) * 8 + S * (N + 1) * 8,
     }
     Kp = ((2 * (N + 1) + 31) // 32) * 32
-    if dom == "k_syrk_mfma":
-        flops = 3.0 * D * (D + 1) * Kp
-        ach = flops / (kern[dom]["avg_ms"] * 1e-3) / 1e12
+    mfma_flops = 3.0 * D * (D + 1) * Kp
+    if dom == role["syrk"]:
+        ach = mfma_flops / (kern[dom]["avg_ms"] * 1e-3) / 1e12
         roof = {"kernel": dom, "bound": "mfma", "achieved": ach, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": ach / BF16_PEAK_TFLOPS, "traffic": traffic}
     else:
@@ -180,15 +185,14 @@ def main():
         roof = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": ach / HBM_PEAK_GBS if ach else None, "traffic": traffic,
                 "alg_bytes": b}
-    mfma_flops = 3.0 * D * (D + 1) * Kp
-    mfma_t = kern.get("k_syrk_mfma", {}).get("avg_ms")
-    contraction_roof = ({"kernel": "k_syrk_mfma", "bound": "mfma", "unit": "TFLOP/s", "peak": BF16_PEAK_TFLOPS,
+    mfma_t = kern.get(role["syrk"], {}).get("avg_ms")
+    contraction_roof = ({"kernel": role["syrk"], "bound": "mfma", "unit": "TFLOP/s", "peak": BF16_PEAK_TFLOPS,
                          "achieved": mfma_flops / (mfma_t * 1e-3) / 1e12,
                          "frac": mfma_flops / (mfma_t * 1e-3) / 1e12 / BF16_PEAK_TFLOPS} if mfma_t else None)
-    spread_t = kern.get("k_spread", {}).get("avg_ms")
-    spread_roof = ({"kernel": "k_spread", "bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
-                    "achieved": alg_bytes["k_spread"] / (spread_t * 1e-3) / 1e9,
-                    "frac": alg_bytes["k_spread"] / (spread_t * 1e-3) / 1e9 / HBM_PEAK_GBS} if spread_t else None)
+    spread_t = kern.get(role["spread"], {}).get("avg_ms")
+    spread_roof = ({"kernel": role["spread"], "bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
+                    "achieved": alg_bytes[role["spread"]] / (spread_t * 1e-3) / 1e9,
+                    "frac": alg_bytes[role["spread"]] / (spread_t * 1e-3) / 1e9 / HBM_PEAK_GBS} if spread_t else None)
 
     out = {
         "metric": "events/s + contraction TFLOP/s at <=1e-5 rel.err vs FP64; speedup vs plain FP64 GPU",

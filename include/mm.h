@@ -76,7 +76,8 @@ typedef struct {
                                   sub-lengths split into register codelets (0: auto) */
     int32_t spread_direct;     /* MM_MIXED spreading: 1 evaluates the kernel formula at every (event, cell)
                                   pair; 2 uses per-tap polynomials (fitted within tol/20) evaluated once per
-                                  event; 0 (auto): polynomials for Kaiser-Bessel, the formula otherwise */
+                                  event; 0 (auto): polynomials for Kaiser-Bessel and ES, the formula for the
+                                  Gaussian */
 } mm_tuning;
 
 /* What the planner chose (host only, no device work). */

@@ -29,6 +29,29 @@ static const double kTwoPi = 6.283185307179586476925286766559;
 __device__ __forceinline__ double2 to_d2(float2 a) { return make_double2(a.x, a.y); }
 __device__ __forceinline__ double2 to_d2(double2 a) { return a; }
 
+#ifndef MM_SYRK_XCD_ORDER
+#define MM_SYRK_XCD_ORDER 1
+#endif
+
+// (split, tile) of a contraction workgroup.  Workgroups are dealt to the eight
+// XCDs in turn (workgroup b runs on XCD b mod 8), each XCD with its own L2.  The
+// XCD-aware order numbers each XCD's workgroups as one contiguous run of the
+// split-major (split, tile) sequence, so the workgroups running side by side on
+// an XCD share a k-range and read the same few row blocks of X through its L2,
+// instead of every workgroup streaming its own operands from HBM.
+__device__ __forceinline__ void syrk_work_item(int b, int ntiles, int nsplit, int& split, int& t)
+{
+    int q = b;
+    if (MM_SYRK_XCD_ORDER) {
+        const int nwg = ntiles * nsplit;
+        const int per = nwg >> 3, rem = nwg & 7;   // XCD x runs per + (x < rem) workgroups
+        const int x = b & 7, r = b >> 3;
+        q = x * per + min(x, rem) + r;
+    }
+    split = q / ntiles;
+    t = q - split * ntiles;
+}
+
 struct SortedCutoffs {
     int n;
     int N[kMaxCutoffs];      // ascending
@@ -239,8 +262,8 @@ __global__ __launch_bounds__(256) void k_syrk_mfma(const uint16_t* __restrict__ 
     __shared__ __align__(16) uint16_t sAl[ST * SLD];
     __shared__ __align__(16) uint16_t sBh[ST * SLD];
     __shared__ __align__(16) uint16_t sBl[ST * SLD];
-    const int split = (int)(blockIdx.x % (unsigned)nsplit);
-    const int t = (int)(blockIdx.x / (unsigned)nsplit);
+    int split, t;
+    syrk_work_item((int)blockIdx.x, ntiles, nsplit, split, t);
     int bi = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
     while (bi * (bi + 1) / 2 > t) --bi;
     while ((bi + 1) * (bi + 2) / 2 <= t) ++bi;
@@ -322,39 +345,6 @@ constexpr int SK2 = 32;
 
 __device__ __forceinline__ int swz(int row, int chunk) { return (row << 2) | (chunk ^ ((row >> 2) & 3)); }
 
-// One stage (32 k) of a wave's 128x128 quadrant from LDS buffer L: per 16 k, the
-// four A row blocks (hi, lo) stay in registers while each B block streams through.
-__device__ __forceinline__ void syrk256_stage(const uint4* __restrict__ L, int ba, int wy, int wx, int lane,
-                                              f32x16 (&acc)[4][4])
-{
-#pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
-        const int ch = 2 * ks + (lane >> 5);
-        bf16x8 fah[4], fal[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            const int r = wy * 128 + a * 32 + (lane & 31);
-            uint4 vh = L[0 * T2 * 4 + swz(r, ch)], vl = L[1 * T2 * 4 + swz(r, ch)];
-            fah[a] = *reinterpret_cast<bf16x8*>(&vh);
-            fal[a] = *reinterpret_cast<bf16x8*>(&vl);
-        }
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int r = wx * 128 + b * 32 + (lane & 31);
-            uint4 vh = L[ba * T2 * 4 + swz(r, ch)], vl = L[(ba + 1) * T2 * 4 + swz(r, ch)];
-            const bf16x8 fbh = *reinterpret_cast<bf16x8*>(&vh), fbl = *reinterpret_cast<bf16x8*>(&vl);
-            // the three products of one block are four MFMAs apart, so no MFMA waits on
-            // the accumulator of the one before it
-#pragma unroll
-            for (int a = 0; a < 4; ++a) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[a], fbh, acc[a][b], 0, 0, 0);
-#pragma unroll
-            for (int a = 0; a < 4; ++a) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[a], fbl, acc[a][b], 0, 0, 0);
-#pragma unroll
-            for (int a = 0; a < 4; ++a) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fal[a], fbh, acc[a][b], 0, 0, 0);
-        }
-    }
-}
-
 // Stage loads: one global_load_lds_dwordx4 per wave fills 1 KB (16 rows of an
 // array); lane p lands in slot p, i.e. row R0 + (p >> 2), physical chunk p & 3, so
 // it fetches logical chunk (p & 3) ^ ((row >> 2) & 3).  Byte offsets fit 32 bits.
@@ -371,14 +361,77 @@ __device__ __forceinline__ void syrk256_load(uint4* L, const char* const (&src)[
     }
 }
 
+#ifndef MM_SYRK_INTERLEAVE
+#define MM_SYRK_INTERLEAVE 1
+#endif
+#ifndef MM_SYRK_LPG
+#define MM_SYRK_LPG 4
+#endif
+
+// One stage (32 k) of a wave's 128x128 quadrant from LDS buffer L: per 16 k, the
+// four A row blocks (hi, lo) stay in registers while each B block streams through.
+// If `load`, the next stage's operands stream into Ln meanwhile, MM_SYRK_LPG loads
+// before each of the first blocks rather than all at once: a burst fills the
+// memory queue and holds the wave at issue until most of it has landed, so the
+// products would wait for the transfer.  The scheduling barriers keep the compiler
+// from gathering the loads again.  A diagonal tile loads only its A panel (arrays
+// 0 and 1).
+__device__ __forceinline__ void syrk256_stage_dma(const uint4* __restrict__ L, uint4* Ln, bool load, bool diag,
+                                                  const char* const (&src)[4], const uint32_t (&goff)[4],
+                                                  uint32_t kbyte, int ba, int wy, int wx, int lane, int wave,
+                                                  f32x16 (&acc)[4][4])
+{
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+        const int ch = 2 * ks + (lane >> 5);
+        bf16x8 fah[4], fal[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const int r = wy * 128 + a * 32 + (lane & 31);
+            uint4 vh = L[0 * T2 * 4 + swz(r, ch)], vl = L[1 * T2 * 4 + swz(r, ch)];
+            fah[a] = *reinterpret_cast<bf16x8*>(&vh);
+            fal[a] = *reinterpret_cast<bf16x8*>(&vl);
+        }
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int r = wx * 128 + b * 32 + (lane & 31);
+            uint4 vh = L[ba * T2 * 4 + swz(r, ch)], vl = L[(ba + 1) * T2 * 4 + swz(r, ch)];
+            if (MM_SYRK_INTERLEAVE) {
+                // 16 loads (array arr, row group q) in groups of LPG before the blocks
+                constexpr int LPG = MM_SYRK_LPG;
+                const int g = ks * 4 + b;
+                if (load && g * LPG < 16) {
+#pragma unroll
+                    for (int u = 0; u < LPG; ++u) {
+                        const int li = g * LPG + u, arr = li >> 2, q = li & 3;
+                        if (arr < 2 || !diag)
+                            __builtin_amdgcn_global_load_lds(src[arr] + goff[q] + kbyte,
+                                                             Ln + (arr * T2 + 16 * (4 * wave + q)) * 4, 16, 0, 0);
+                    }
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            const bf16x8 fbh = *reinterpret_cast<bf16x8*>(&vh), fbl = *reinterpret_cast<bf16x8*>(&vl);
+            // the three products of one block are four MFMAs apart, so no MFMA waits on
+            // the accumulator of the one before it
+#pragma unroll
+            for (int a = 0; a < 4; ++a) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[a], fbh, acc[a][b], 0, 0, 0);
+#pragma unroll
+            for (int a = 0; a < 4; ++a) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[a], fbl, acc[a][b], 0, 0, 0);
+#pragma unroll
+            for (int a = 0; a < 4; ++a) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fal[a], fbh, acc[a][b], 0, 0, 0);
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void k_syrk_mfma256(const uint16_t* __restrict__ hi,
                                                       const uint16_t* __restrict__ lo, int64_t Kp, int64_t kchunk,
                                                       int ntiles, int nsplit, float* __restrict__ partial)
 {
     __shared__ uint4 lds0[4 * T2 * 4];   // [array: A hi, A lo, B hi, B lo][row][chunk], even stages
     __shared__ uint4 lds1[4 * T2 * 4];   // odd stages
-    const int split = (int)(blockIdx.x % (unsigned)nsplit);
-    const int t = (int)(blockIdx.x / (unsigned)nsplit);
+    int split, t;
+    syrk_work_item((int)blockIdx.x, ntiles, nsplit, split, t);
     int bi = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
     while (bi * (bi + 1) / 2 > t) --bi;
     while ((bi + 1) * (bi + 2) / 2 <= t) ++bi;
@@ -407,18 +460,30 @@ __global__ __launch_bounds__(256) void k_syrk_mfma256(const uint16_t* __restrict
             for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
     const int ba = diag ? 0 : 2;   // arrays holding the B panel
     const uint32_t kb0 = (uint32_t)kb * 2u;
+    // The wave holding the upper quadrant of a diagonal tile only loads.  Stage s reads buffer s mod 2 while stage s+1 loads into the other; the two
+    // buffers are addressed statically (a pair of stages per iteration) so that the
+    // compiler sees that the loads never touch the buffer being read.
     if (nst > 0) syrk256_load(lds0, src, goff, kb0, wave, diag);
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
     for (int s = 0; s < nst; s += 2) {
-        // even stage from lds0 while odd stage s+1 loads into lds1
-        if (s + 1 < nst) syrk256_load(lds1, src, goff, kb0 + (uint32_t)(s + 1) * SK2 * 2u, wave, diag);
-        if (active) syrk256_stage(lds0, ba, wy, wx, lane, acc);
+        const bool l1 = s + 1 < nst;
+        if (!MM_SYRK_INTERLEAVE && l1) syrk256_load(lds1, src, goff, kb0 + (uint32_t)(s + 1) * SK2 * 2u, wave, diag);
+        if (active)
+            syrk256_stage_dma(lds0, lds1, l1, diag, src, goff, kb0 + (uint32_t)(s + 1) * SK2 * 2u, ba, wy, wx, lane,
+                              wave, acc);
+        else if (MM_SYRK_INTERLEAVE && l1)
+            syrk256_load(lds1, src, goff, kb0 + (uint32_t)(s + 1) * SK2 * 2u, wave, diag);
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
-        if (s + 1 >= nst) break;
-        if (s + 2 < nst) syrk256_load(lds0, src, goff, kb0 + (uint32_t)(s + 2) * SK2 * 2u, wave, diag);
-        if (active) syrk256_stage(lds1, ba, wy, wx, lane, acc);
+        if (!l1) break;
+        const bool l2 = s + 2 < nst;
+        if (!MM_SYRK_INTERLEAVE && l2) syrk256_load(lds0, src, goff, kb0 + (uint32_t)(s + 2) * SK2 * 2u, wave, diag);
+        if (active)
+            syrk256_stage_dma(lds1, lds0, l2, diag, src, goff, kb0 + (uint32_t)(s + 2) * SK2 * 2u, ba, wy, wx, lane,
+                              wave, acc);
+        else if (MM_SYRK_INTERLEAVE && l2)
+            syrk256_load(lds0, src, goff, kb0 + (uint32_t)(s + 2) * SK2 * 2u, wave, diag);
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
     }
@@ -659,14 +724,15 @@ hipError_t launch_cov_mfma(int32_t G, int32_t D, const void* coef, int64_t ldc, 
         prof_begin("k_split_bf16", st);
         hipLaunchKernelGGL(k_split_bf16, dim3(bx, s.Dp), dim3(256), 0, st, D, (int)s.Dp, cg, ldc, N, basis, s.Kp, hi, lo);
         prof_end("k_split_bf16", st);
-        prof_begin("k_syrk_mfma", st);
+        const char* syrk_name = s.ts == T2 ? "k_syrk_mfma256" : "k_syrk_mfma";
+        prof_begin(syrk_name, st);
         if (s.ts == T2)
             hipLaunchKernelGGL(k_syrk_mfma256, dim3((unsigned)(s.ntiles * s.nsplit)), dim3(256), 0, st, hi, lo, s.Kp,
                                s.kchunk, s.ntiles, s.nsplit, part);
         else
             hipLaunchKernelGGL(k_syrk_mfma, dim3((unsigned)(s.ntiles * s.nsplit)), dim3(256), 0, st, hi, lo, s.Kp,
                                s.kchunk, s.ntiles, s.nsplit, part);
-        prof_end("k_syrk_mfma", st);
+        prof_end(syrk_name, st);
         prof_begin("k_syrk_reduce", st);
         if (s.ts == T2)
             hipLaunchKernelGGL(k_syrk_reduce<T2>, dim3((unsigned)(16 * s.ntiles)), dim3(256), 0, st, part, s.nsplit,

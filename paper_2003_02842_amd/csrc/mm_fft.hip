@@ -460,19 +460,19 @@ static hipError_t fft_ab_t(const Plan& p, const NufftWs& w, char* ws, int32_t s_
 {
     using C = typename CTf<T>::type;
     const int t1 = round64(p.CC * std::max(p.A1, p.B1));
-    prof_begin("k_fft_cols", st);
+    prof_begin("k_fft_cols_ab", st);
     hipLaunchKernelGGL(k_fft_cols_ab<T>, dim3((p.L2 + p.CC - 1) / p.CC, s_count), dim3(t1), fft_ab_lds_cols(p), st,
                        grid, gstride, p.L1, p.L2, p.L2p, p.A1, p.B1, p.CC, (const C*)(ws + w.tw1),
                        (const C*)(ws + w.tLlo), (const C*)(ws + w.tLhi), p.tw_lo_bits, p.tw_hi_L);
-    prof_end("k_fft_cols", st);
+    prof_end("k_fft_cols_ab", st);
     const int P = p.L1 / 2 + 1;
     const int t2 = round64(std::max(2 * p.RR * std::max(p.A2, p.B2), 64));
-    prof_begin("k_fft_rows", st);
+    prof_begin("k_fft_rows_ab", st);
     hipLaunchKernelGGL(k_fft_rows_ab<T>, dim3((P + p.RR - 1) / p.RR, s_count), dim3(t2), fft_ab_lds_rows(p), st,
                        grid, gstride, p.L1, p.L2, p.L2p, p.A2, p.B2, p.RR, (const C*)(ws + w.tw2),
                        (const C*)(ws + w.tMlo), (const C*)(ws + w.tMhi), p.tw_lo_bits, p.tw_hi_M,
                        (const T*)(ws + w.dfac), p.N, (C*)coef, ldc, s_begin);
-    prof_end("k_fft_rows", st);
+    prof_end("k_fft_rows_ab", st);
     return hipGetLastError();
 }
 

@@ -1066,7 +1066,9 @@ static hipError_t nufft_tiled_t(const Plan& p, const NufftWs& w, char* ws, int32
         hipLaunchKernelGGL(k_tile_ranges<false>, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, st, offsets, t,
                            s_begin, s_count, tiles, p.tile, p.Mr, p.kp.w, p.kp.hw, t0, span, (double)p.Mr / span, ranges);
     prof_end("k_tile_ranges", st);
-    prof_begin("k_spread", st);
+    // recorded under the name of the kernel that runs
+    const char* spread_name = (sizeof(T) == 4 && p.poly) ? "k_spread_poly" : "k_spread";
+    prof_begin(spread_name, st);
     if constexpr (sizeof(T) == 4) {
         if (p.poly) {
             hipError_t e = launch_spread_poly(p, s_count, t, dp, dp_fp64, t0, T_, ranges, tiles, grid, gstride, st);
@@ -1082,7 +1084,7 @@ static hipError_t nufft_tiled_t(const Plan& p, const NufftWs& w, char* ws, int32
         else
             launch_spread_k<T, float>(p, s_count, t, (const float*)dp, t0, T_, ranges, tiles, grid, gstride, st);
     }
-    prof_end("k_spread", st);
+    prof_end(spread_name, st);
 
     if (p.fft_ab) return launch_fft_ab(p, w, ws, s_begin, s_count, grid, gstride, coef, ldc, st);
     const int cbs = ilog2(p.CB);

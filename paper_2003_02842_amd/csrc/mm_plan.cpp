@@ -437,13 +437,14 @@ mm_status make_plan(int32_t N, mm_kernel kernel, double tol, mm_prec prec, const
         if (p->fft_ab && (fft_ab_lds_rows(*p) > 64 * 1024 || fft_ab_lds_cols(*p) > 64 * 1024)) p->fft_ab = 0;
     }
     // FP32 spreading from per-tap polynomials when they stay well inside tol.  By
-    // default only for Kaiser-Bessel, whose formula (sinh/sin branches) is the
-    // costliest per tap; ES and Gaussian taps measured faster evaluated directly in
-    // the gather (2.9 vs 3.7 ms and 3.6 vs 4.8 ms on the large universe).
+    // default for Kaiser-Bessel (its sinh/sin formula is the costliest per tap) and
+    // ES (2.7 vs 2.9-3.2 ms on the large universe, and closer to FP64); the Gaussian
+    // needs wider kernels, whose longer tap records make the formula faster there
+    // (3.6 vs 4.8 ms).
     p->poly = 0;
     p->poly_err = 0.0;
     const int sd = tune ? tune->spread_direct : 0;
-    const bool want_poly = sd == 2 || (sd == 0 && kernel == MM_KAISER_BESSEL);
+    const bool want_poly = sd == 2 || (sd == 0 && kernel != MM_GAUSSIAN);
     if (prec == MM_MIXED && p->kp.w <= kMaxPolyTaps && want_poly) {
         const double err = fit_poly(p->kp, poly_degree_for_width(p->kp.w), &p->pp);
         if (err <= 0.05 * tol) {

@@ -214,3 +214,20 @@ def test_spread_formula_and_polynomial_paths(mm, kernel, mode, tol):
     for s, n in enumerate(counts):
         if n:
             assert err[s] <= tol * 2 + 2e-7, (s, n, err[s])
+
+
+@pytest.mark.parametrize("tile", [1024, 2048, 4096])
+@pytest.mark.parametrize("per_cell", [0.02, 1.0, 4.0, 12.0, 80.0])
+def test_polynomial_spreading_at_every_density(mm, tile, per_cell):
+    """The per-tap polynomial gather splits a cell pair's events over 1, 2, 4 or 8
+    lanes depending on how many cells a chunk of events reaches; densities from
+    0.02 to 80 events per grid cell take every split, over several tiles and the
+    periodic wrap."""
+    N = 2100
+    plan = mm.plan_query(N, "es", 1e-6, "mixed", {"spread_direct": 2, "tile": tile})
+    n = max(1, int(per_cell * plan["Mr"]))
+    w = synth.random_events(1, n, n, seed=int(per_cell * 100) + tile, dp_dtype=torch.float32)
+    c = gpu_coef(mm, w, N, "es", 1e-6, "mixed", {"spread_direct": 2, "tile": tile})
+    ref = oracle_coef(w, N)
+    err = series_rel_l2(c, ref)
+    assert err[0] <= 2e-6 + 2e-7, (n, plan["Mr"], err[0])
