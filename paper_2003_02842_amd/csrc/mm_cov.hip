@@ -227,19 +227,34 @@ __device__ __forceinline__ uint16_t bf16_rne(float x)
 __device__ __forceinline__ float bf16_to_f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 // X (Dp x Kp, zero padded) from float2 coefficients: column 2k+e = s_k (Re, Im)_e c_k.
-__global__ void k_split_bf16(int D, int Dp, const float2* __restrict__ coef, int64_t ldc, int N, int basis,
-                             int64_t Kp, uint16_t* __restrict__ hi, uint16_t* __restrict__ lo)
+// Column scale of X: s_k = 2pi sqrt(m_k w_k) for k <= N (FP64, rounded once), 0 on
+// the padding, so that the split reads one float per column instead of forming
+// the weight per element.
+__global__ void k_split_scale(int N, int basis, int64_t Kh, float* __restrict__ scale)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= Kh) return;
+    float v = 0.f;
+    if (k <= N) {
+        const double Nd = (double)N;
+        const double w = (basis == MM_DIRICHLET) ? 1.0 / (2.0 * Nd + 1.0) : (1.0 - (double)k / Nd) / (Nd + 1.0);
+        v = (float)(kTwoPi * sqrt((k ? 2.0 : 1.0) * w));
+    }
+    scale[k] = v;
+}
+
+__global__ void k_split_bf16(int D, const float2* __restrict__ coef, int64_t ldc, int N,
+                             const float* __restrict__ scale, int64_t Kp, uint16_t* __restrict__ hi,
+                             uint16_t* __restrict__ lo)
 {
     const int64_t row = blockIdx.y;
-    const double Nd = (double)N;
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < Kp / 2; c += (int64_t)gridDim.x * blockDim.x) {
         float2 v = make_float2(0.f, 0.f);
-        int k = (int)c;
+        const int k = (int)c;
         if (row < D && k <= N) {
-            double w = (basis == MM_DIRICHLET) ? 1.0 / (2.0 * Nd + 1.0) : (1.0 - (double)k / Nd) / (Nd + 1.0);
-            float s = (float)(kTwoPi * sqrt((k ? 2.0 : 1.0) * w));
-            float2 cc = coef[row * ldc + k];
-            v = make_float2(cc.x * s, cc.y * s);
+            const float sc = scale[k];
+            const float2 cc = coef[row * ldc + k];
+            v = make_float2(cc.x * sc, cc.y * sc);
         }
         uint16_t h0 = bf16_rne(v.x), h1 = bf16_rne(v.y);
         uint16_t l0 = bf16_rne(v.x - bf16_to_f(h0)), l1 = bf16_rne(v.y - bf16_to_f(h1));
@@ -248,12 +263,9 @@ __global__ void k_split_bf16(int D, int Dp, const float2* __restrict__ coef, int
     }
 }
 
-// One workgroup = one lower-triangle 128x128 tile over one k-range.  The
-// workgroups of a k-range are numbered split + nsplit * tile; workgroups are
-// dispatched round-robin over the 8 XCDs, so with nsplit a multiple of 8 every
-// k-range stays on one XCD and the tiles sharing a row panel read it through
-// that XCD's L2 (measured at D = 2000, N = 50000: 1.63 ms against 2.35 ms when
-// each XCD holds whole tiles over all k).
+// One workgroup = one lower-triangle 128x128 tile over one k-range, numbered in
+// the XCD-aware order of syrk_work_item, so that the tiles sharing a row panel
+// read it through one XCD's L2.
 __global__ __launch_bounds__(256) void k_syrk_mfma(const uint16_t* __restrict__ hi, const uint16_t* __restrict__ lo,
                                                    int64_t Kp, int64_t kchunk, int ntiles, int nsplit,
                                                    float* __restrict__ partial)
@@ -501,16 +513,21 @@ __global__ __launch_bounds__(256) void k_syrk_mfma256(const uint16_t* __restrict
             }
 }
 
-// Sum of the k-range partials of one 64x64 sub-block of a lower-triangle tile,
-// written to Sigma at (i, j) and, through an LDS transpose, at (j, i).
+// Sum of the k-range partials of 16 rows x 64 columns of a lower-triangle tile
+// (workgroup = tile, 64x64 sub-block, quarter of it), written to Sigma at (i, j)
+// and, through an LDS transpose, at (j, i).  Each thread keeps four partial sums
+// so that four loads of the split are in flight at once.
 template <int TS>
 __global__ __launch_bounds__(256) void k_syrk_reduce(const float* __restrict__ partial, int nsplit, int ntiles, int D,
                                                      float* __restrict__ cov)
 {
     constexpr int ST = TS;
     constexpr int QN = TS / 64;   // 64 x 64 sub-blocks per tile edge
-    __shared__ float tileT[64][65];
-    const int t = blockIdx.x / (QN * QN), quad = blockIdx.x % (QN * QN);
+    constexpr int RB = 16;        // rows per workgroup
+    __shared__ float tileT[RB][65];
+    const int per_tile = QN * QN * (64 / RB);
+    const int t = blockIdx.x / per_tile, rem = blockIdx.x % per_tile;
+    const int quad = rem / (64 / RB), part = rem % (64 / RB);
     int bi = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
     while (bi * (bi + 1) / 2 > t) --bi;
     while ((bi + 1) * (bi + 2) / 2 <= t) ++bi;
@@ -520,10 +537,19 @@ __global__ __launch_bounds__(256) void k_syrk_reduce(const float* __restrict__ p
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     const int64_t tstride = (int64_t)ntiles * ST * ST;
     const float* P = partial + (int64_t)t * ST * ST;
-    for (int r = ty; r < 64; r += 4) {
-        const int li = qi + r, lj = qj + tx;
-        float acc = 0.f;
-        for (int q = 0; q < nsplit; ++q) acc += P[q * tstride + li * ST + lj];
+    for (int r = ty; r < RB; r += 4) {
+        const int li = qi + part * RB + r, lj = qj + tx;
+        const float* p = P + li * ST + lj;
+        float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+        int q = 0;
+        for (; q + 3 < nsplit; q += 4) {
+            a0 += p[q * tstride];
+            a1 += p[(q + 1) * tstride];
+            a2 += p[(q + 2) * tstride];
+            a3 += p[(q + 3) * tstride];
+        }
+        for (; q < nsplit; ++q) a0 += p[q * tstride];
+        const float acc = (a0 + a1) + (a2 + a3);
         const int i = bi * ST + li, j = bj * ST + lj;
         if (bi == bj) {
             // diagonal tile: (i, j) and (j, i) both come from the lower entry, so that
@@ -539,10 +565,11 @@ __global__ __launch_bounds__(256) void k_syrk_reduce(const float* __restrict__ p
     }
     if (bi == bj) return;
     __syncthreads();
-    for (int r = ty; r < 64; r += 4) {
-        // row j = bj*ST + qj + r of Sigma, columns i = bi*ST + qi + tx
-        const int j = bj * ST + qj + r, i = bi * ST + qi + tx;
-        if (i < D && j < D) cov[(int64_t)j * D + i] = tileT[tx][r];
+    // rows j = bj*ST + qj + c (c < 64) of Sigma, columns i = bi*ST + qi + part*RB + r (r < RB)
+    for (int e = threadIdx.x; e < 64 * RB; e += 256) {
+        const int c = e / RB, r = e % RB;
+        const int j = bj * ST + qj + c, i = bi * ST + qi + part * RB + r;
+        if (i < D && j < D) cov[(int64_t)j * D + i] = tileT[r][c];
     }
 }
 
@@ -656,7 +683,7 @@ struct MfmaShape {
     int ts;               // tile edge: 128 or 256
     int tn, ntiles, nsplit;
     int64_t Dp, Kp, kchunk;
-    size_t hi, lo, partial, total;
+    size_t hi, lo, partial, scale, total;
 };
 
 static MfmaShape mfma_shape(int32_t D, int32_t N)
@@ -679,6 +706,7 @@ static MfmaShape mfma_shape(int32_t D, int32_t N)
         s.hi = o; o += al((size_t)s.Dp * s.Kp * 2);
         s.lo = o; o += al((size_t)s.Dp * s.Kp * 2);
         s.partial = o; o += al((size_t)s.nsplit * s.ntiles * T2 * T2 * 4);
+        s.scale = o; o += al((size_t)s.Kp / 2 * 4);
         s.total = o;
         return s;
     }
@@ -701,6 +729,7 @@ static MfmaShape mfma_shape(int32_t D, int32_t N)
     s.hi = o; o += al((size_t)s.Dp * s.Kp * 2);
     s.lo = o; o += al((size_t)s.Dp * s.Kp * 2);
     s.partial = o; o += al((size_t)s.nsplit * s.ntiles * ST * ST * 4);
+    s.scale = o; o += al((size_t)s.Kp / 2 * 4);
     s.total = o;
     return s;
 }
@@ -718,11 +747,17 @@ hipError_t launch_cov_mfma(int32_t G, int32_t D, const void* coef, int64_t ldc, 
     uint16_t* hi = (uint16_t*)(ws + s.hi);
     uint16_t* lo = (uint16_t*)(ws + s.lo);
     float* part = (float*)(ws + s.partial);
+    float* scale = (float*)(ws + s.scale);
+    prof_begin("k_split_scale", st);
+    hipLaunchKernelGGL(k_split_scale, dim3((unsigned)((s.Kp / 2 + 255) / 256)), dim3(256), 0, st, N, basis, s.Kp / 2,
+                       scale);
+    prof_end("k_split_scale", st);
     for (int g = 0; g < G; ++g) {
         const float2* cg = (const float2*)coef + (int64_t)g * D * ldc;
         int bx = (int)std::min<int64_t>((s.Kp / 2 + 255) / 256, 64);
         prof_begin("k_split_bf16", st);
-        hipLaunchKernelGGL(k_split_bf16, dim3(bx, s.Dp), dim3(256), 0, st, D, (int)s.Dp, cg, ldc, N, basis, s.Kp, hi, lo);
+        hipLaunchKernelGGL(k_split_bf16, dim3(bx, s.Dp), dim3(256), 0, st, D, cg, ldc, N, (const float*)scale, s.Kp,
+                           hi, lo);
         prof_end("k_split_bf16", st);
         const char* syrk_name = s.ts == T2 ? "k_syrk_mfma256" : "k_syrk_mfma";
         prof_begin(syrk_name, st);
@@ -735,10 +770,10 @@ hipError_t launch_cov_mfma(int32_t G, int32_t D, const void* coef, int64_t ldc, 
         prof_end(syrk_name, st);
         prof_begin("k_syrk_reduce", st);
         if (s.ts == T2)
-            hipLaunchKernelGGL(k_syrk_reduce<T2>, dim3((unsigned)(16 * s.ntiles)), dim3(256), 0, st, part, s.nsplit,
+            hipLaunchKernelGGL(k_syrk_reduce<T2>, dim3((unsigned)(64 * s.ntiles)), dim3(256), 0, st, part, s.nsplit,
                                s.ntiles, D, (float*)cov + (int64_t)g * D * D);
         else
-            hipLaunchKernelGGL(k_syrk_reduce<ST>, dim3((unsigned)(4 * s.ntiles)), dim3(256), 0, st, part, s.nsplit,
+            hipLaunchKernelGGL(k_syrk_reduce<ST>, dim3((unsigned)(16 * s.ntiles)), dim3(256), 0, st, part, s.nsplit,
                                s.ntiles, D, (float*)cov + (int64_t)g * D * D);
         prof_end("k_syrk_reduce", st);
     }

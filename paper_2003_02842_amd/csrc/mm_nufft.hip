@@ -519,7 +519,7 @@ __global__ __launch_bounds__(256) void k_spread_poly(const double* __restrict__ 
 {
     constexpr int TC = 512 * PPT;
     constexpr int M = (W + 2) & ~1;                      // even ring, >= W + 1
-    constexpr int EC = (M <= 12) ? MM_POLY_CHUNK : MM_POLY_CHUNK / 2;   // ~25 KB of LDS: 6 workgroups per CU
+    constexpr int EC = (M <= 12 || MM_POLY_CHUNK <= 256) ? MM_POLY_CHUNK : MM_POLY_CHUNK / 2;   // ~25 KB of LDS
     constexpr int SB = EC / 256;
     constexpr int DEG = poly_degree_for_width(W);
     __shared__ __align__(8) float ring[EC * M];
