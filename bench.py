@@ -99,6 +99,37 @@ def copy_calibration():
     return 0
 
 
+def measured_peaks():
+    """Reference rates on this device: a 2 GiB device-to-device copy (HBM GB/s,
+    bytes read + written) and a 8192^3 BF16 library GEMM (TFLOP/s), best of 5."""
+    import torch
+    n = 2 << 30
+    src = torch.empty(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    a = torch.randn(8192, 8192, device="cuda", dtype=torch.bfloat16)
+    b = torch.randn(8192, 8192, device="cuda", dtype=torch.bfloat16)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def best(fn):
+        fn()
+        torch.cuda.synchronize()
+        t = float("inf")
+        for _ in range(5):
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            t = min(t, e0.elapsed_time(e1))
+        return t
+
+    copy_ms = best(lambda: dst.copy_(src))
+    gemm_ms = best(lambda: torch.mm(a, b))
+    out = {"hbm_copy_gbs": 2 * n / (copy_ms * 1e-3) / 1e9, "bf16_gemm_tflops": 2 * 8192 ** 3 / (gemm_ms * 1e-3) / 1e12}
+    del src, dst, a, b
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     a = parse()
     if a.copy_calibration:
@@ -143,7 +174,7 @@ def main():
     # kernel names as launched (the planner picks one kernel per role)
     roles = {"spread": ("k_spread_poly", "k_spread"), "fft_cols": ("k_fft_cols_ab", "k_fft_cols"),
              "fft_rows": ("k_fft_rows_ab", "k_fft_rows"), "syrk": ("k_syrk_mfma256", "k_syrk_mfma")}
-    names = ["k_prep", "k_tile_ranges", "k_split_bf16", "k_syrk_reduce", "k_corr", "k_cov_small"] + \
+    names = ["k_prep", "k_tile_ranges", "k_split_scale", "k_split_bf16", "k_syrk_reduce", "k_corr", "k_cov_small"] + \
         [n for r in roles.values() for n in r]
     kern = {}
     for nm in names:
@@ -158,7 +189,7 @@ def main():
     # contraction throughput (GEMM-equivalent flops)
     K = 2 * N + 1
     gemm_flops = 2.0 * D * D * K
-    t_con = sum(kern[k]["avg_ms"] for k in ("k_split_bf16", role["syrk"], "k_syrk_reduce") if k in kern)
+    t_con = sum(kern[k]["avg_ms"] for k in ("k_split_scale", "k_split_bf16", role["syrk"], "k_syrk_reduce") if k in kern)
     con_tflops = gemm_flops / (t_con * 1e-3) / 1e12 if t_con > 0 else None
 
     # roofline of the dominant kernel: algorithmic bytes (flops) per launch over the
@@ -216,6 +247,7 @@ def main():
         "roofline": roof,
         "roofline_spread": spread_roof,
         "roofline_contraction": contraction_roof,
+        "measured_peaks": measured_peaks(),
     }
 
     # plain FP64 GPU form on the same input with the same kernel width (so the same
