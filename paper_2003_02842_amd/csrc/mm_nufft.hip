@@ -546,6 +546,16 @@ __global__ __launch_bounds__(256) void k_spread_poly(const double* __restrict__ 
     float acc0[PPT], acc1[PPT];
 #pragma unroll
     for (int r = 0; r < PPT; ++r) acc0[r] = acc1[r] = 0.f;
+    // leading coefficients of each tap's even and odd Horner chains, held in vector
+    // registers for the whole kernel: the first step of a chain then reads one
+    // scalar operand instead of two (one scalar operand per instruction)
+    float ctop[(W + 1) / 2][2];
+#pragma unroll
+    for (int j = 0; j < (W + 1) / 2; ++j) {
+        ctop[j][0] = pp.c[j][DEG & ~1];
+        ctop[j][1] = pp.c[j][(DEG - 1) | 1];
+        asm volatile("" : "+v"(ctop[j][0]), "+v"(ctop[j][1]));
+    }
     double tv[SB];
     DPT dv[SB];
     if (total_chunks > 0) {
@@ -572,30 +582,31 @@ __global__ __launch_bounds__(256) void k_spread_poly(const double* __restrict__ 
                 const int key = (int)(l0 - shift) + W - 1;   // >= 0; tap j reaches cell key - W + 1 + j
                 const float sv = (float)(f - 0.5);
                 const float v = (float)dv[u];
-                float* o = ring + i * M;
-                const int base = (key - W + 1 + M) % M;     // slot of tap 0: (key - W + 1) mod M, key >= 0
-                // tap j = E_j(s^2) + s O_j(s^2) and, by the kernel's symmetry, tap W-1-j =
-                // E_j(s^2) - s O_j(s^2): even and odd coefficients by Horner in s^2
-                const float s2 = sv * sv;
+                // tap j = v (E_j(s^2) + s O_j(s^2)) and, by the kernel's symmetry, tap W-1-j =
+                // v (E_j(s^2) - s O_j(s^2)): even and odd coefficients by Horner in s^2,
+                // the return folded in as v E_j and (v s) O_j
+                const float s2 = sv * sv, vs = v * sv;
                 float tap[W];
 #pragma unroll
                 for (int j = 0; j < (W + 1) / 2; ++j) {
                     constexpr int DE = DEG & ~1, DO = (DEG - 1) | 1;   // top even and odd powers
-                    float ev = pp.c[j][DE], od = pp.c[j][DO];
+                    float ev = fmaf(ctop[j][0], s2, pp.c[j][DE - 2]), od = fmaf(ctop[j][1], s2, pp.c[j][DO - 2]);
 #pragma unroll
-                    for (int k = DE - 2; k >= 0; k -= 2) ev = fmaf(ev, s2, pp.c[j][k]);
+                    for (int k = DE - 4; k >= 0; k -= 2) ev = fmaf(ev, s2, pp.c[j][k]);
 #pragma unroll
-                    for (int k = DO - 2; k >= 1; k -= 2) od = fmaf(od, s2, pp.c[j][k]);
-                    const float sod = sv * od;
-                    tap[j] = v * (ev + sod);
-                    if (W - 1 - j != j) tap[W - 1 - j] = v * (ev - sod);
+                    for (int k = DO - 4; k >= 1; k -= 2) od = fmaf(od, s2, pp.c[j][k]);
+                    const float vev = v * ev;
+                    tap[j] = fmaf(vs, od, vev);
+                    if (W - 1 - j != j) tap[W - 1 - j] = fmaf(-vs, od, vev);
                 }
+                // slot of tap j: base + j, or base + j - M past the end of the ring; each
+                // store picks one of two row pointers and adds j as a constant offset
+                const int base = (key - W + 1 + M) % M;     // slot of tap 0: (key - W + 1) mod M, key >= 0
+                const int r1 = 4 * (i * M + base), r2 = r1 - 4 * M;   // byte offsets of the two rows
+                char* const rb = reinterpret_cast<char*>(ring);
 #pragma unroll
-                for (int j = 0; j < M; ++j) {
-                    int sl = base + j;
-                    sl = sl >= M ? sl - M : sl;
-                    o[sl] = j < W ? tap[j] : 0.f;
-                }
+                for (int j = 0; j < M; ++j)
+                    *reinterpret_cast<float*>(rb + (j < M - base ? r1 : r2) + 4 * j) = j < W ? tap[j] : 0.f;
                 keys[i] = (unsigned short)key;
             }
         }
@@ -609,14 +620,20 @@ __global__ __launch_bounds__(256) void k_spread_poly(const double* __restrict__ 
             }
         }
         __syncthreads();
-        const int kmin = keys[0], kmax = keys[n - 1];
+        // the chunk's key range, the same for every lane: held in scalar registers
+        const int kmin = __builtin_amdgcn_readfirstlane(keys[0]);
+        const int kmax = __builtin_amdgcn_readfirstlane(keys[n - 1]);
         for (int i = 1 + threadIdx.x; i < n; i += 256) {
             const int k1 = keys[i];
             for (int k = keys[i - 1] + 1; k <= k1; ++k) first[k] = (unsigned short)i;
         }
         __syncthreads();
+        // rounds whose cell pairs (c, c+1), c = 2 (tid + 256 r), can meet the chunk:
+        // kmin - W <= c <= kmax; the others are skipped by a scalar branch
+        const int r_lo = max(kmin - W, 0) >> 9, r_hi = kmax >> 9;
 #pragma unroll
         for (int r = 0; r < PPT; ++r) {
+            if (r < r_lo || r > r_hi) continue;
             const int c = 2 * ((int)threadIdx.x + 256 * r);
             if (c >= len || c + W < kmin || c > kmax) continue;
             const int lo = (c <= kmin) ? 0 : first[c];
