@@ -686,6 +686,31 @@ struct MfmaShape {
     size_t hi, lo, partial, scale, total;
 };
 
+// k-ranges per 256-wide tile: the workgroups (tiles x ranges) run in rounds of 256
+// (one per CU), so the time goes as ceil(tiles s / 256) / s of one tile's full k
+// range, plus the partial tiles each range writes and the reduce reads back.  The
+// smallest s within 10% of the best modelled time wins (shorter ranges cost more
+// than the model counts: D = 3000 measured slower at 13 ranges than at 3), and
+// each range keeps >= 64 stages.  Model rates: 4.7 TFLOP/s of products per CU,
+// 5 TB/s for the partials.
+static int split_count(int ntiles, int64_t Kp)
+{
+    const double c_k = 256.0 * 256.0 * 6.0 / 4.7e12;      // s per k column of one tile on one CU
+    const double c_p = 2.0 * 256.0 * 256.0 * 4.0 / 5.0e12;   // s per partial tile written and read
+    int best_s = 1;
+    double best_t = 0.0;
+    for (int sp = 1; sp <= 64; ++sp) {
+        if (sp > 1 && Kp / sp < 64 * SK2) break;
+        const double rounds = (double)((ntiles * (int64_t)sp + 255) / 256);
+        const double t = rounds / sp * (double)Kp * c_k + (double)sp * ntiles * c_p;
+        if (sp == 1 || t < 0.90 * best_t) {
+            best_s = sp;
+            best_t = t;
+        }
+    }
+    return best_s;
+}
+
 static MfmaShape mfma_shape(int32_t D, int32_t N)
 {
     MfmaShape s;
@@ -698,7 +723,7 @@ static MfmaShape mfma_shape(int32_t D, int32_t N)
         s.tn = tn2;
         s.ntiles = s.tn * (s.tn + 1) / 2;
         s.Dp = (int64_t)s.tn * T2;
-        s.nsplit = std::max(1, 256 / s.ntiles);
+        s.nsplit = split_count(s.ntiles, s.Kp);
         const int64_t per = (s.Kp + s.nsplit - 1) / s.nsplit;
         s.kchunk = ((per + SK2 - 1) / SK2) * SK2;
         auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
