@@ -23,6 +23,10 @@
 
 #include "mm_internal.h"
 
+#ifndef MM_FFT_ROWS_XCD
+#define MM_FFT_ROWS_XCD 1
+#endif
+
 namespace mm {
 
 template <typename T> struct CTf;
@@ -331,10 +335,24 @@ __global__ __launch_bounds__(512) void k_fft_rows_ab(const T* __restrict__ grid,
     for (int i = threadIdx.x; i < L2; i += blockDim.x) tw2[i] = tw2g[i];
     for (int i = threadIdx.x; i < (1 << lo_bits); i += blockDim.x) lo[i] = log_[i];
     for (int i = threadIdx.x; i < n_hi; i += blockDim.x) hi[i] = hig[i];
-    const C* Y = reinterpret_cast<const C*>(grid + (int64_t)blockIdx.y * grid_stride);
-    C* out = coef + (int64_t)(s_out + blockIdx.y) * ldc;
+    // Work item (row block bx, series by) in an XCD-aware order: workgroups are dealt
+    // to the eight XCDs in turn, and each XCD takes a contiguous run of the
+    // row-block-major sequence, so that the row blocks whose outputs share 128-byte
+    // lines (k = k1 + L1 k2 with consecutive k1) are written through one L2 at
+    // about the same time rather than as partial lines from several.
+    int bx = (int)blockIdx.x, by = (int)blockIdx.y;
+    if (MM_FFT_ROWS_XCD) {
+        const int nwg = (int)(gridDim.x * gridDim.y);
+        const int lin = (int)(blockIdx.x + gridDim.x * blockIdx.y);
+        const int per = nwg >> 3, rem = nwg & 7, x = lin & 7, r = lin >> 3;
+        const int w = x * per + min(x, rem) + r;
+        bx = w % (int)gridDim.x;
+        by = w / (int)gridDim.x;
+    }
+    const C* Y = reinterpret_cast<const C*>(grid + (int64_t)by * grid_stride);
+    C* out = coef + (int64_t)(s_out + by) * ldc;
     const int P = L1 / 2 + 1;
-    const int p0 = blockIdx.x * RR;
+    const int p0 = bx * RR;
     const int nr = min(RR, P - p0);
     // LDS row 2i: matrix row p0 + i; row 2i + 1: its mirror
     auto mrow = [&](int r) { const int p = p0 + (r >> 1); return (r & 1) ? (L1 - p) % L1 : p; };
