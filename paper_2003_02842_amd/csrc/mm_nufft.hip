@@ -1,27 +1,32 @@
 // gfx950 kernels of the type-1 NUFFT (Sec. 2.2.5 of the paper):
-//   k_prep      FP64 tables: FFT twiddles, digit-reversal maps, deconvolution
-//               factors 1/(2 pi psi_hat(k/Mr)) of the averaging kernel
+//   k_prep         FP64 tables: FFT twiddles, digit-reversal maps, deconvolution
+//                  factors 1/(2 pi psi_hat(k/Mr)) of the averaging kernel
 //   k_tile_ranges  per (series, grid tile) event ranges by binary search on the
-//               sorted event keys
-//   k_spread    spreading onto the periodic oversampled grid (Eq. Der:15), one
-//               workgroup per (series, grid tile), each cell gathering its events
-//               from LDS; no atomics
-//   k_fft_cols  first pass of the grid FFT (Eq. Der:16): length-L1 transforms of
-//               strided columns of the L1 x L2 view of the packed complex grid,
-//               times the four-step twiddle, in place
-//   k_fft_rows  second pass: length-L2 transforms of rows, the real-input
-//               untangling, deconvolution (Eq. Der:17) and the 1/2pi of the
-//               coefficient definition; writes c_k, k = 0..N
+//                  sorted event keys
+//   k_spread       spreading onto the periodic oversampled grid (Eq. Der:15), one
+//                  workgroup per (series, grid tile), each cell gathering its
+//                  events from LDS and evaluating the kernel formula per pair; no
+//                  atomics
+//   k_spread_poly  the same sum in FP32 from per-tap polynomials evaluated once per
+//                  event into LDS rings, then gathered per cell pair
+//   k_fft_cols, k_fft_rows
+//                  generic grid FFT (Eq. Der:16) with in-LDS mixed-radix passes,
+//                  used where the two-pass register-codelet form (mm_fft.hip)
+//                  does not apply: length-L1 transforms of the strided columns of
+//                  the L1 x L2 view of the packed complex grid times the four-step
+//                  twiddle, then length-L2 transforms of the rows with the
+//                  real-input untangling, deconvolution (Eq. Der:17) and the 1/2pi
+//                  of the coefficient definition; writes c_k, k = 0..N
 //
 // The real grid x[0..Mr) is FFT'd as the complex sequence z_j = x_2j + i x_2j+1
-// of length L = Mr/2 = L1 L2; every sub-transform is an in-place mixed-radix
-// (4, 5, 3, 2) decimation-in-frequency FFT in LDS whose output sits in
-// digit-reversed positions.
+// of length L = Mr/2 = L1 L2; in the generic passes every sub-transform is an
+// in-place mixed-radix (4, 5, 3, 2) decimation-in-frequency FFT in LDS whose
+// output sits in digit-reversed positions.
 #include <hip/hip_runtime.h>
 
 #include "mm_internal.h"
 
-// Events staged per LDS chunk by the FP32 spreading kernels (multiples of 512).
+// Events staged per LDS chunk by the FP32 spreading kernels (multiples of 256).
 #ifndef MM_SPREAD_CHUNK
 #define MM_SPREAD_CHUNK 2048
 #endif
