@@ -561,18 +561,23 @@ __global__ __launch_bounds__(256) void k_spread_poly(const double* __restrict__ 
         ctop[j][1] = pp.c[j][(DEG - 1) | 1];
         asm volatile("" : "+v"(ctop[j][0]), "+v"(ctop[j][1]));
     }
-    double tv[SB];
-    DPT dv[SB];
-    if (total_chunks > 0) {
-        int64_t cb; int n, m;
-        locate(0, cb, n, m);
+    // Chunk staging runs two chunks ahead: two register sets alternate, so that the
+    // loads of chunk q+1 are already in flight while chunk q is staged, and those of
+    // chunk q+2 are issued as soon as chunk q's registers are free.
+    // The loads are unconditional (past the end of a chunk, or past the last chunk,
+    // they repeat its last event), so every path issues the same loads and the
+    // compiler's wait before staging a chunk leaves the other set in flight.
+    auto load_chunk = [&](int qq, double (&tvx)[SB], DPT (&dvx)[SB]) {
+        int64_t cb2; int n2, m2;
+        locate(min(qq, total_chunks - 1), cb2, n2, m2);
 #pragma unroll
         for (int u = 0; u < SB; ++u) {
-            const int i = (int)threadIdx.x + 256 * u;
-            if (i < n) { tv[u] = t[cb + i]; dv[u] = dp[cb + i]; }
+            const int64_t ii = cb2 + min((int)threadIdx.x + 256 * u, n2 - 1);
+            tvx[u] = t[ii];
+            dvx[u] = dp[ii];
         }
-    }
-    for (int q = 0; q < total_chunks; ++q) {
+    };
+    auto chunk = [&](int q, double (&tv)[SB], DPT (&dv)[SB]) {
         int64_t cb; int n, m;
         locate(q, cb, n, m);
         const int64_t shift = (int64_t)a + (int64_t)(m - 1) * Mr;
@@ -615,15 +620,8 @@ __global__ __launch_bounds__(256) void k_spread_poly(const double* __restrict__ 
                 keys[i] = (unsigned short)key;
             }
         }
-        if (q + 1 < total_chunks) {
-            int64_t cb2; int n2, m2;
-            locate(q + 1, cb2, n2, m2);
-#pragma unroll
-            for (int u = 0; u < SB; ++u) {
-                const int i = (int)threadIdx.x + 256 * u;
-                if (i < n2) { tv[u] = t[cb2 + i]; dv[u] = dp[cb2 + i]; }
-            }
-        }
+        // this register set is free again: load the chunk after next into it
+        load_chunk(q + 2, tv, dv);
         __syncthreads();
         // the chunk's key range, the same for every lane: held in scalar registers
         const int kmin = __builtin_amdgcn_readfirstlane(keys[0]);
@@ -665,6 +663,17 @@ __global__ __launch_bounds__(256) void k_spread_poly(const double* __restrict__ 
             acc0[r] += (s0 + u0) + (p0 + q0);
             acc1[r] += (s1 + u1) + (p1 + q1);
         }
+        };
+    double tva[SB], tvb[SB];
+    DPT dva[SB], dvb[SB];
+    if (total_chunks > 0) {
+        load_chunk(0, tva, dva);
+        load_chunk(1, tvb, dvb);
+    }
+    for (int q = 0; q < total_chunks; q += 2) {
+        chunk(q, tva, dva);
+        if (q + 1 >= total_chunks) break;
+        chunk(q + 1, tvb, dvb);
     }
     // cells (c, c+1) are complex entry j = (a + c)/2 at row j / L2, column j % L2
     float2* out = reinterpret_cast<float2*>(grid + (int64_t)blockIdx.y * grid_stride);
