@@ -8,10 +8,9 @@
  *        c_k = (1/2pi) sum_h delta_h exp(-i k tilde t_h),  k = 0..N
  *      (Sec. 2.2, the equation defining F(dp_i)(k)), computed by a type-1
  *      non-uniform FFT (Sec. 2.2.5, Eqs. Der:14-17): spread the events onto an
- *      oversampled periodic grid with a Gaussian (Eq. Der:5/7, fast Gaussian
- *      gridding Eq. Der:20), Kaiser-Bessel (Eqs. Der:8-9) or exponential of
- *      semicircle (Eqs. Der:10-11) kernel, FFT the grid, divide by the kernel's
- *      Fourier transform.  Negative k follow from c_{-k} = conj(c_k) (real
+ *      oversampled periodic grid with a Gaussian (Eqs. Der:5, 7), Kaiser-Bessel
+ *      (Eqs. Der:8-9) or exponential of semicircle (Eqs. Der:10-11) kernel, FFT
+ *      the grid, divide by the kernel's Fourier transform.  Negative k follow from c_{-k} = conj(c_k) (real
  *      returns, Sec. 2.2.2) and are not stored.
  *
  *   2. mm_cov: the Dirichlet (Eq. Der:2) or Fejer (Eq. Der:3) estimate
@@ -255,7 +254,9 @@ const char* mm_status_string(mm_status s);
 /* Per-kernel timing: when enabled, every kernel the library launches is
  * bracketed by HIP events on its stream; mm_profile_read synchronises those
  * events and returns the summed duration and launch count of the kernels whose
- * name equals `kernel_name` (host string), NULL meaning all. */
+ * name equals `kernel_name` (host string: the launched kernel's own name, e.g.
+ * "k_spread_poly", "k_fft_rows_ab", "k_syrk_mfma256"), NULL meaning all.  Launches
+ * inside a graph capture are not timed. */
 mm_status mm_profile_enable(int32_t on);
 mm_status mm_profile_read(const char* kernel_name, double* total_ms /* host */, int64_t* launches /* host */);
 mm_status mm_profile_reset(void);
