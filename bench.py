@@ -174,7 +174,7 @@ def main():
     # kernel names as launched (the planner picks one kernel per role)
     roles = {"spread": ("k_spread_poly", "k_spread"), "fft_cols": ("k_fft_cols_ab", "k_fft_cols"),
              "fft_rows": ("k_fft_rows_ab", "k_fft_rows"), "syrk": ("k_syrk_mfma256", "k_syrk_mfma")}
-    names = ["k_prep", "k_tile_ranges", "k_split_scale", "k_split_bf16", "k_syrk_reduce", "k_corr", "k_cov_small"] + \
+    names = ["k_prep", "k_deconv", "k_fft_tables", "k_tile_ranges", "k_split_scale", "k_split_bf16", "k_syrk_reduce", "k_corr", "k_cov_small"] + \
         [n for r in roles.values() for n in r]
     kern = {}
     for nm in names:

@@ -1,6 +1,7 @@
 // gfx950 kernels of the type-1 NUFFT (Sec. 2.2.5 of the paper):
-//   k_prep         FP64 tables: FFT twiddles, digit-reversal maps, deconvolution
-//                  factors 1/(2 pi psi_hat(k/Mr)) of the averaging kernel
+//   k_prep         FP64 tables of the generic FFT passes: twiddles, digit-reversal maps
+//   k_deconv       deconvolution factors 1/(2 pi psi_hat(k/Mr)) of the averaging
+//                  kernel, one wave per k
 //   k_tile_ranges  per (series, grid tile) event ranges by binary search on the
 //                  sorted event keys
 //   k_spread       spreading onto the periodic oversampled grid (Eq. Der:15), one
@@ -951,9 +952,9 @@ __device__ int digit_pos(int k, const FFTDesc& F)
 }
 
 template <typename T>
-__global__ void k_prep(int L1, int L2, int L, int Mr, int N, KernParams kp, FFTDesc F1, FFTDesc F2, GLRule gl,
-                       typename CT<T>::type* tw1, typename CT<T>::type* tw2, typename CT<T>::type* twL,
-                       typename CT<T>::type* twM, int* rev1, int* pos2, T* dfac)
+__global__ void k_prep(int L1, int L2, int L, int Mr, FFTDesc F1, FFTDesc F2, typename CT<T>::type* tw1,
+                       typename CT<T>::type* tw2, typename CT<T>::type* twL, typename CT<T>::type* twM, int* rev1,
+                       int* pos2)
 {
     using C = typename CT<T>::type;
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -973,8 +974,32 @@ __global__ void k_prep(int L1, int L2, int L, int Mr, int N, KernParams kp, FFTD
     if (i < L1) { rev1[i] = digit_rev((int)i, F1); return; }
     i -= L1;
     if (i < L2) { pos2[i] = digit_pos((int)i, F2); return; }
-    i -= L2;
-    if (i <= N) { dfac[i] = (T)deconv_factor(kp, (int)i, Mr, gl); return; }
+}
+
+// Deconvolution factors 1/(2 pi psi_hat(k/Mr)), k = 0..N: one wave per k.  The ES
+// transform (Eq. Der:11) is a Gauss-Legendre sum over the rule's 2 x 64 symmetric
+// nodes, one node per lane, added up by lane shuffles; the Gaussian and KB
+// transforms have closed forms (lane 0).
+template <typename T>
+__global__ __launch_bounds__(64) void k_deconv(int N, int Mr, KernParams kp, GLRule gl, T* __restrict__ dfac)
+{
+    const int k = blockIdx.x;
+    if (k > N) return;
+    const int q = threadIdx.x;
+    const double pi = 3.14159265358979323846;
+    if (kp.kind == MM_ES) {
+        const double nu = (double)k / (double)Mr;
+        double acc = 0.0;
+        for (int n = q; n < kGLNodes; n += 64) {
+            const double z = gl.x[n];
+            acc += gl.w[n] * exp(kp.es_beta * (sqrt(1.0 - z * z) - 1.0)) * cospi(2.0 * nu * kp.hw * z);
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
+        if (q == 0) dfac[k] = (T)(1.0 / (2.0 * pi * (2.0 * kp.hw * acc)));
+    } else if (q == 0) {
+        dfac[k] = (T)deconv_factor(kp, k, Mr, gl);
+    }
 }
 
 __global__ void k_validate(int32_t S, const int64_t* __restrict__ offsets, const double* __restrict__ t,
@@ -1015,18 +1040,29 @@ hipError_t ensure_constants(int) { return hipSuccess; }
 hipError_t launch_prep(const Plan& p, const NufftWs& w, char* ws, hipStream_t st)
 {
     GLRule gl = host_gl();
-    int64_t total = 2ll * p.L1 + 2ll * p.L2 + 2ll * p.L + (p.N + 1);
-    int blocks = (int)((total + 255) / 256);
-    prof_begin("k_prep", st);
+    // the generic FFT passes' tables (the two-pass form has its own, k_fft_tables)
+    if (!p.fft_ab) {
+        const int64_t total = 2ll * p.L1 + 2ll * p.L2 + 2ll * p.L;
+        const int blocks = (int)((total + 255) / 256);
+        prof_begin("k_prep", st);
+        if (p.prec == MM_MIXED)
+            hipLaunchKernelGGL(k_prep<float>, dim3(blocks), dim3(256), 0, st, p.L1, p.L2, p.L, p.Mr, p.F1, p.F2,
+                               (float2*)(ws + w.tw1), (float2*)(ws + w.tw2), (float2*)(ws + w.twL),
+                               (float2*)(ws + w.twM), (int*)(ws + w.rev1), (int*)(ws + w.pos2));
+        else
+            hipLaunchKernelGGL(k_prep<double>, dim3(blocks), dim3(256), 0, st, p.L1, p.L2, p.L, p.Mr, p.F1, p.F2,
+                               (double2*)(ws + w.tw1), (double2*)(ws + w.tw2), (double2*)(ws + w.twL),
+                               (double2*)(ws + w.twM), (int*)(ws + w.rev1), (int*)(ws + w.pos2));
+        prof_end("k_prep", st);
+    }
+    prof_begin("k_deconv", st);
     if (p.prec == MM_MIXED)
-        hipLaunchKernelGGL(k_prep<float>, dim3(blocks), dim3(256), 0, st, p.L1, p.L2, p.L, p.Mr, p.N, p.kp, p.F1,
-                           p.F2, gl, (float2*)(ws + w.tw1), (float2*)(ws + w.tw2), (float2*)(ws + w.twL),
-                           (float2*)(ws + w.twM), (int*)(ws + w.rev1), (int*)(ws + w.pos2), (float*)(ws + w.dfac));
+        hipLaunchKernelGGL(k_deconv<float>, dim3(p.N + 1), dim3(64), 0, st, p.N, p.Mr, p.kp, gl,
+                           (float*)(ws + w.dfac));
     else
-        hipLaunchKernelGGL(k_prep<double>, dim3(blocks), dim3(256), 0, st, p.L1, p.L2, p.L, p.Mr, p.N, p.kp, p.F1,
-                           p.F2, gl, (double2*)(ws + w.tw1), (double2*)(ws + w.tw2), (double2*)(ws + w.twL),
-                           (double2*)(ws + w.twM), (int*)(ws + w.rev1), (int*)(ws + w.pos2), (double*)(ws + w.dfac));
-    prof_end("k_prep", st);
+        hipLaunchKernelGGL(k_deconv<double>, dim3(p.N + 1), dim3(64), 0, st, p.N, p.Mr, p.kp, gl,
+                           (double*)(ws + w.dfac));
+    prof_end("k_deconv", st);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess && p.fft_ab) e = launch_fft_ab_tables(p, w, ws, st);
     return e;
