@@ -103,7 +103,7 @@ static hipError_t enqueue_nufft(const Plan& p, const NufftWs& w, char* wsb, int3
     return e;
 }
 
-static int small_d_limit(int32_t D) { return D * (D + 1) / 2 <= 1024; }
+static int small_d_limit(int32_t D) { return (int64_t)D * (D + 1) / 2 <= 1024; }
 
 // The contraction for every cutoff, then the correlation (host checks already done).
 static hipError_t enqueue_cov(int32_t G, int32_t D, const void* coef, int64_t ldc, const int32_t* Ns, int32_t nN,

@@ -716,7 +716,10 @@ static MfmaShape mfma_shape(int32_t D, int32_t N)
     MfmaShape s;
     s.Kp = ((2ll * (N + 1) + SK - 1) / SK) * SK;
     const int tn2 = (D + T2 - 1) / T2;
-    if (MM_SYRK_BIG_TILES && tn2 >= 4 && s.Kp / SK2 >= 64) {
+    // the 256-wide kernel addresses a panel with 32-bit byte offsets (row x Kp x 2 for
+    // rows < 256, plus the k offset); beyond that the 128-wide kernel (64-bit) runs
+    const bool offsets32 = (s.Kp * 2) * 257 < (1ll << 32);
+    if (MM_SYRK_BIG_TILES && tn2 >= 4 && s.Kp / SK2 >= 64 && offsets32) {
         // 256-wide tiles, about one workgroup per CU, so every tile's k-range runs
         // concurrently and the partials stay few
         s.ts = T2;
