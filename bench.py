@@ -48,6 +48,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU-oracle sample time")
     ap.add_argument("--width", type=int, default=0, help="override the spreading width")
+    ap.add_argument("--sigma", type=float, default=0.0, help="override the oversampling factor")
+    ap.add_argument("--untuned", action="store_true",
+                    help="the planner's defaults (sigma = 2) instead of the autotuned large-universe plan")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy (scales FETCH_SIZE/WRITE_SIZE counters)")
     return ap.parse_args()
@@ -57,7 +60,8 @@ PROFILE_TRAFFIC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "prof
 
 
 def source_hash() -> str:
-    """First 16 hex digits of the SHA-256 over the library's kernel sources."""
+    """First 16 hex digits of the SHA-256 over the library's kernel sources and
+    the tuned plan the default run uses."""
     import glob
     import hashlib
     h = hashlib.sha256()
@@ -65,6 +69,8 @@ def source_hash() -> str:
     for f in sorted(glob.glob(os.path.join(here, "paper_2003_02842_amd", "csrc", "*"))):
         with open(f, "rb") as fh:
             h.update(fh.read())
+    from paper_2003_02842_amd.tune import LARGE_UNIVERSE
+    h.update(repr(sorted(LARGE_UNIVERSE.items())).encode())
     return h.hexdigest()[:16]
 
 
@@ -149,7 +155,10 @@ def main():
     E, S, N, D = w.E, w.S, a.N, a.D
     print("# generated %d events in %.1f s" % (E, t_gen), file=sys.stderr, flush=True)
 
-    tune = {"width": a.width} if a.width else None
+    from paper_2003_02842_amd.tune import LARGE_UNIVERSE
+    tune = {} if a.untuned else dict(LARGE_UNIVERSE)
+    tune.update({k: v for k, v in (("width", a.width), ("sigma", a.sigma)) if v})
+    tune = tune or None
     plan = mm.plan_query(N, a.kernel, a.tol, "mixed", tune)
     coef = torch.empty((S, N + 1), dtype=torch.complex64, device=dev)
     ws1 = torch.empty(mm.nufft1_workspace_size(S, N, a.kernel, a.tol, "mixed", tune), dtype=torch.uint8, device=dev)
@@ -195,8 +204,8 @@ def main():
     # roofline of the dominant kernel: algorithmic bytes (flops) per launch over the
     # mean launch duration from HIP events on the launch stream
     dom = max(kern, key=lambda k: kern[k]["avg_ms"])
-    default_workload = (a.D, a.n_lo, a.n_hi, a.N, a.kernel, a.tol, a.basis, a.seed, a.width) == \
-        (2000, 1e4, 1e6, 50_000, "es", 1e-6, "fejer", 20200310, 0)
+    default_workload = (a.D, a.n_lo, a.n_hi, a.N, a.kernel, a.tol, a.basis, a.seed, a.width, a.sigma, a.untuned) == \
+        (2000, 1e4, 1e6, 50_000, "es", 1e-6, "fejer", 20200310, 0, 0.0, False)
     traffic = measured_traffic(dom) if default_workload else None
     Mr = plan["Mr"]
     alg_bytes = {
@@ -240,7 +249,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "large-universe: D=%d 3-factor GBM, log-uniform counts [%g, %g], T=28800 s, N=%d, "
                                "%s kernel, %s basis" % (D, a.n_lo, a.n_hi, N, a.kernel, a.basis),
-                   "events": E, "series": S, "N": N, "tol": a.tol, "width": plan["width"], "Mr": Mr,
+                   "events": E, "series": S, "N": N, "tol": a.tol, "width": plan["width"], "sigma": plan["sigma"], "Mr": Mr,
+                   "tuning": tune,
                    "seed": a.seed, "parallelism": "1 GPU"},
         "contraction_tflops": con_tflops,
         "kernels_ms": {k: round(v["avg_ms"], 5) for k, v in kern.items()},
@@ -255,7 +265,7 @@ def main():
     if not a.no_plain:
         dp64 = w.dp.to(torch.float64)
         coef64 = torch.empty((S, N + 1), dtype=torch.complex128, device=dev)
-        ptune = {"width": plan["width"]}
+        ptune = {"width": plan["width"], "sigma": plan["sigma"]}
         wsp = torch.empty(mm.nufft1_workspace_size(S, N, a.kernel, a.tol, "fp64", ptune), dtype=torch.uint8,
                           device=dev)
 

@@ -47,7 +47,8 @@ typedef enum {
     MM_OK = 0,
     MM_ERR_ARG = 1,          /* a size, pointer or enum argument is invalid */
     MM_ERR_DATA = 2,         /* validate=1 found unsorted, out-of-window or non-finite events */
-    MM_ERR_TOL = 3,          /* tol outside [1e-14,1e-1] (FP64) or [1e-6,1e-1] (mixed) */
+    MM_ERR_TOL = 3,          /* tol outside [1e-14,1e-1] (FP64) or [1e-6,1e-1] (mixed), or
+                                out of reach at the requested oversampling */
     MM_ERR_WORKSPACE = 4,    /* ws_bytes below the size the *_workspace_size call reports */
     MM_ERR_HIP = 5,          /* a HIP runtime call failed */
     MM_ERR_UNSUPPORTED = 6   /* a valid request this build does not implement */
@@ -91,16 +92,20 @@ typedef struct {
     double sigma;              /* oversampling factor used in the kernel shape rules */
     double beta;               /* ES beta, Gaussian lambda or Kaiser-Bessel b */
     double tol;
-    double est_err;            /* a-priori bound on the relative coefficient error (aliasing of the truncated
-                                  kernel plus deconvolution mismatch), excluding floating-point rounding */
+    double est_err;            /* a-priori bound on the relative coefficient error: aliasing of the truncated
+                                  kernel plus deconvolution mismatch (worst case over k); on the mixed path the
+                                  FP32 rounding term 2^-24 G rms_k psi_hat(0)/psi_hat(k/Mr) instead when larger
+                                  (G measured per evaluation: 2 polynomials, 4.5 ES, 6.5 Gaussian, 10
+                                  Kaiser-Bessel formula) */
 } mm_plan_info;
 
 /* Plan of a type-1 NUFFT of cutoff N (Sec. 2.2.5): the spreading width follows
  * the paper's tolerance rules (Sec. 2.2.5, with the ES rule's M_sp + 2) on the
- * FP64 path and the smallest width meeting tol by the a-priori estimate on the
- * mixed path; the grid is Mr = smallest even 2,3,5-smooth length
- * >= max(sigma(2N+1), 2 width, 8) with sigma = 2 (Sec. 2.2.5), unless `tune`
- * overrides.  Host only. */
+ * FP64 path at sigma = 2 (and for the Gaussian, whose rule carries sigma), and
+ * otherwise is the smallest width whose a-priori estimate (est_err) meets tol; the
+ * grid is Mr = smallest even 2,3,5-smooth length >= max(sigma(2N+1), 2 width, 8)
+ * with sigma = 2 (Sec. 2.2.5), unless `tune` overrides.  MM_ERR_TOL also when
+ * no width up to 40 meets tol at the requested sigma.  Host only. */
 mm_status mm_plan_query(int32_t N, mm_kernel kernel, double tol, mm_prec prec,
                         const mm_tuning* tune, mm_plan_info* out /* host */);
 

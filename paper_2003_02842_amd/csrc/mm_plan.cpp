@@ -267,19 +267,51 @@ static double estimate_error_uncached(const KernParams& kp, int Mr, int N)
     return worst;
 }
 
-static std::mutex g_est_mu;
-static std::map<std::tuple<int, int, long long, long long, int, int>, double> g_est_cache;
+// FP32 rounding on the mixed path.  The spread grid and its transform carry
+// relative errors of a few units of u = 2^-24, and the deconvolution (Eq. Der:17)
+// multiplies the error at frequency k by psi_hat(0) / psi_hat(k / Mr), which
+// grows quickly as sigma falls towards 1.  For a flat spectrum the relative l2
+// error of the coefficients is u G rms_k psi_hat(0) / psi_hat(k / Mr); G was
+// measured against the FP64 oracle over sigma = 1.25..2.5 (ES,
+// Gaussian and Kaiser-Bessel, uneven series up to 4 events per cell): 1.2-2.2
+// with per-tap polynomials, 3.6-4.2 with the ES formula, 4.5-6.0 with the
+// Gaussian formula and 6.5-9.8 with the Kaiser-Bessel formula.
+static double rounding_gain(int kernel, bool poly)
+{
+    if (poly) return 2.0;
+    if (kernel == MM_KAISER_BESSEL) return 10.0;
+    return kernel == MM_GAUSSIAN ? 6.5 : 4.5;
+}
 
-static double estimate_error(const KernParams& kp, double sigma, int Mr, int N)
+static double rounding_error(const KernParams& kp, int Mr, int N, double gain)
+{
+    const int samples = 65;
+    const double d0 = host_psihat_deconv(kp, 0.0);
+    double acc = 0.0;
+    for (int i = 0; i < samples; ++i) {
+        const double r = d0 / host_psihat_deconv(kp, (double)N * i / (samples - 1) / Mr);
+        acc += r * r;
+    }
+    return 0x1p-24 * gain * sqrt(acc / samples);
+}
+
+static std::mutex g_est_mu;
+static std::map<std::tuple<int, int, long long, long long, int, int, int>, double> g_est_cache;
+
+// Aliasing and truncation (a worst case over k, well above the l2 error they
+// cause), or the FP32 rounding term when `gain` > 0 (the mixed path) and it is
+// larger.
+static double estimate_error(const KernParams& kp, double sigma, int Mr, int N, double gain)
 {
     auto key = std::make_tuple(kp.kind, kp.w, (long long)llround(sigma * 1e6), (long long)llround(kp.es_beta * 1e6),
-                               Mr, N);
+                               Mr, N, (int)llround(gain * 1000));
     {
         std::lock_guard<std::mutex> lk(g_est_mu);
         auto it = g_est_cache.find(key);
         if (it != g_est_cache.end()) return it->second;
     }
     double e = estimate_error_uncached(kp, Mr, N);
+    if (gain > 0) e = std::max(e, rounding_error(kp, Mr, N, gain));
     std::lock_guard<std::mutex> lk(g_est_mu);
     g_est_cache[key] = e;
     return e;
@@ -373,13 +405,17 @@ mm_status make_plan(int32_t N, mm_kernel kernel, double tol, mm_prec prec, const
     }
     p->msp = msp;
     const int req = tune ? tune->width : 0;
+    const int sd = tune ? tune->spread_direct : 0;
+    const bool want_poly = sd == 2 || (sd == 0 && kernel != MM_GAUSSIAN);
     if (req > 0) {
         w = req;
         if (kernel == MM_GAUSSIAN && (w & 1)) ++w;
         if (kernel == MM_KAISER_BESSEL && !(w & 1)) ++w;
         msp = msp_for_width(kernel, w);
-    } else if (req == 0 && prec == MM_MIXED) {
-        // smallest width whose worst-case error estimate meets tol
+    } else if (req == 0 && (prec == MM_MIXED || (kernel != MM_GAUSSIAN && sg != 2.0))) {
+        // smallest width whose worst-case error estimate meets tol (the FP64
+        // path keeps the rules above at sigma = 2, the oversampling they are
+        // stated for; the Gaussian's rule already carries sigma)
         const int step = (kernel == MM_ES) ? 1 : 2;
         int wa = (kernel == MM_KAISER_BESSEL) ? 3 : 2;
         bool found = false;
@@ -389,16 +425,18 @@ mm_status make_plan(int32_t N, mm_kernel kernel, double tol, mm_prec prec, const
             if (ma < 1) continue;
             set_kernel(q.kp, kernel, wa, ma, sg, tune);
             if (set_grid(&q) != MM_OK) continue;
-            if (estimate_error(q.kp, sg, q.Mr, N) <= tol) { found = true; break; }
+            const double gain = (prec == MM_MIXED) ? rounding_gain(kernel, want_poly && wa <= kMaxPolyTaps) : 0.0;
+            if (estimate_error(q.kp, sg, q.Mr, N, gain) <= tol) { found = true; break; }
         }
-        if (found) { w = wa; msp = msp_for_width(kernel, w); }
+        if (!found) return MM_ERR_TOL;   // tol out of reach at this oversampling
+        w = wa;
+        msp = msp_for_width(kernel, w);
     }
     if (w < 2 || w > kMaxTaps || msp < 1) return MM_ERR_ARG;
     p->wmsp = msp;
     set_kernel(p->kp, kernel, w, msp, sg, tune);
     mm_status gs = set_grid(p);
     if (gs != MM_OK) return gs;
-    p->est_err = estimate_error(p->kp, sg, p->Mr, N);
     {
         const int q = (prec == MM_MIXED) ? 16 : 8;   // complex values per 128 bytes
         p->L2p = (p->L2 + q - 1) / q * q;
@@ -443,8 +481,6 @@ mm_status make_plan(int32_t N, mm_kernel kernel, double tol, mm_prec prec, const
     // (3.6 vs 4.8 ms).
     p->poly = 0;
     p->poly_err = 0.0;
-    const int sd = tune ? tune->spread_direct : 0;
-    const bool want_poly = sd == 2 || (sd == 0 && kernel != MM_GAUSSIAN);
     if (prec == MM_MIXED && p->kp.w <= kMaxPolyTaps && want_poly) {
         const double err = fit_poly(p->kp, poly_degree_for_width(p->kp.w), &p->pp);
         if (err <= 0.05 * tol) {
@@ -452,6 +488,7 @@ mm_status make_plan(int32_t N, mm_kernel kernel, double tol, mm_prec prec, const
             p->poly_err = err;
         }
     }
+    p->est_err = estimate_error(p->kp, sg, p->Mr, N, (prec == MM_MIXED) ? rounding_gain(kernel, p->poly) : 0.0);
     int tile = (prec == MM_MIXED) ? 2048 : 1024;
     if (tune && tune->tile > 0) tile = tune->tile <= 1024 ? 1024 : (tune->tile <= 2048 ? 2048 : 4096);
     p->tile = tile;

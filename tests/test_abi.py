@@ -137,10 +137,19 @@ def test_mixed_default_width_meets_estimate(kern, tol):
 
 @pytest.mark.parametrize("kern", ["es", "kb", "g"])
 def test_error_estimate_decreases_with_width(kern):
+    """The aliasing/truncation estimate (the FP64 path's) falls with every added
+    tap.  The mixed path's estimate also covers FP32 rounding, which the
+    deconvolution amplifies more as the kernel widens: it is never below the
+    FP64 one, stops falling, and never drops under one unit of 2^-24."""
     step = 1 if kern == "es" else 2
     w0 = 3 if kern == "kb" else 2
-    ests = [mm.plan_query(500, kern, 1e-6, "mixed", {"width": w})["est_err"] for w in range(w0, 17, step)]
+    ws = range(w0, 17, step)
+    ests = [mm.plan_query(500, kern, 1e-6, "fp64", {"width": w})["est_err"] for w in ws]
     assert all(b < a for a, b in zip(ests, ests[1:]))
+    mixed = [mm.plan_query(500, kern, 1e-6, "mixed", {"width": w})["est_err"] for w in ws]
+    assert all(m >= f for m, f in zip(mixed, ests))
+    assert mixed[0] == ests[0] and min(mixed) >= 2.0 ** -24
+    assert mixed[-1] > ests[-1]
 
 
 def test_fp64_default_is_paper_rule():

@@ -29,10 +29,11 @@ def mm():
 @pytest.fixture(scope="module")
 def universe(mm):
     """The benchmark workload: 2000 assets, ~4.5e8 events, N = 50,000, mixed ES
-    tol 1e-6, Fejer basis -- the same calls bench.py times."""
+    tol 1e-6, Fejer basis, the autotuned plan -- the same calls bench.py times."""
+    from paper_2003_02842_amd.tune import LARGE_UNIVERSE
     w = synth.large_universe(device="cuda")
     N = w.Ns[0]
-    coef = mm.nufft1(w.offsets, w.t, w.dp, w.t0, w.T, N, "es", 1e-6, "mixed")
+    coef = mm.nufft1(w.offsets, w.t, w.dp, w.t0, w.T, N, "es", 1e-6, "mixed", dict(LARGE_UNIVERSE))
     cov, corr = mm.cov(coef, 1, w.S, [N], "fejer")
     torch.cuda.synchronize()
     return w, N, coef, cov[0, 0].cpu().numpy().astype(np.float64), corr[0, 0].cpu().numpy().astype(np.float64)

@@ -216,13 +216,56 @@ def test_spread_formula_and_polynomial_paths(mm, kernel, mode, tol):
             assert err[s] <= tol * 2 + 2e-7, (s, n, err[s])
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed", 1e-6)])
+@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("sigma", [1.25, 1.55, 1.65, 2.5])
+@pytest.mark.parametrize("kernel", ["es", "kb"])
+def test_oversampling_factors(mm, prec, tol, mode, sigma, kernel):
+    """Oversampling factors other than 2 (the planner widens the kernel until its
+    error estimate, FP32 rounding included, is under tol: w = 9, 9, 7 for ES at
+    tol 1e-6 and sigma = 1.55, 1.65, 2.5), both FP32 evaluations, uneven series
+    with a dense one, Sigma/R at two cutoffs.  At sigma = 1.25 the deconvolution
+    amplifies rounding (by ~40 at the band edge) past tol for every width, and
+    the planner must say so; the per-pair formula, with more rounding than the
+    polynomials, is refused at some of the other factors too."""
+    N = 2700
+    tune = {"sigma": sigma, "spread_direct": mode, "tile": 2048}
+    if sigma == 1.25:
+        with pytest.raises(mm.MMError, match="status 3"):
+            mm.plan_query(N, kernel, tol, prec, tune)
+        return
+    try:
+        info = mm.plan_query(N, kernel, tol, prec, tune)
+    except mm.MMError as e:
+        assert "status 3" in str(e) and prec == "mixed" and mode == 1, e
+        return
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    w = synth.random_events(7, 0, 2500, seed=91, dp_dtype=dt)
+    dense = synth.random_events(1, 40_000, 40_000, seed=92, dp_dtype=dt)
+    w = synth.Workload("ragged", torch.cat([w.offsets, w.offsets[-1] + dense.offsets[1:]]),
+                       torch.cat([w.t, dense.t]), torch.cat([w.dp, dense.dp]), 0.0, 1.0, 1, 8, [1], 0, {})
+    assert info["Mr"] >= sigma * (2 * N + 1)
+    c = gpu_coef(mm, w, N, kernel, tol, prec, tune)
+    ref = oracle_coef(w, N)
+    err = series_rel_l2(c, ref)
+    counts = (w.offsets[1:] - w.offsets[:-1]).tolist()
+    bar = tol * 2 + (2e-7 if prec == "mixed" else 1e-14)
+    for s, n in enumerate(counts):
+        if n:
+            assert err[s] <= bar, (info["width"], info["Mr"], s, n, err[s])
+    S, R = mm.cov(c, 1, 8, [N, 300], "fejer")
+    So, Ro = oracle.cov(ref, 1, 8, [N, 300], oracle.FEJER)
+    bar2 = FP64_BAR if prec == "fp64" else MIXED_BAR
+    assert relfro(S.cpu().numpy(), So) <= bar2
+    assert relfro(R.cpu().numpy(), Ro) <= bar2
+
+
 @pytest.mark.parametrize("tile", [1024, 2048, 4096])
 @pytest.mark.parametrize("per_cell", [0.02, 1.0, 4.0, 12.0, 80.0])
 def test_polynomial_spreading_at_every_density(mm, tile, per_cell):
-    """The per-tap polynomial gather splits a cell pair's events over 1, 2, 4 or 8
-    lanes depending on how many cells a chunk of events reaches; densities from
-    0.02 to 80 events per grid cell take every split, over several tiles and the
-    periodic wrap."""
+    """Densities from 0.02 to 80 events per grid cell: tiles holding a handful
+    of events (one chunk, most cell pairs empty) up to tiles that take many LDS
+    chunks, over several tiles and the periodic wrap."""
     N = 2100
     plan = mm.plan_query(N, "es", 1e-6, "mixed", {"spread_direct": 2, "tile": tile})
     n = max(1, int(per_cell * plan["Mr"]))
