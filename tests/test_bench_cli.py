@@ -1,5 +1,6 @@
-"""bench.py's command-line contract that needs no GPU: any GPU count other than one
-is refused with a message and exit status 2, before anything touches a device."""
+"""bench.py's command-line contract that needs no GPU: any GPU count other than one,
+and any unknown workload, is refused with a message and exit status 2, before
+anything touches a device."""
 import os
 import subprocess
 import sys
@@ -13,3 +14,9 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode == 2
     assert "exactly one GPU" in r.stderr
     assert r.stdout.strip() == ""
+
+
+def test_unknown_workload_is_rejected():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--workload", "no-such-workload"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2 and "invalid choice" in r.stderr
