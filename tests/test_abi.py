@@ -152,6 +152,23 @@ def test_error_estimate_decreases_with_width(kern):
     assert mixed[-1] > ests[-1]
 
 
+def test_rounding_floor_refuses_low_oversampling():
+    """At sigma = 1.25 the deconvolution amplifies FP32 rounding by ~40 (rms over
+    the band), so no width meets tol 1e-6 on the mixed path, and FP64 cannot
+    reach 1e-12 there; at sigma = 1.55 the mixed plan exists and its estimate
+    covers the rounding term 2^-24 * 2 * rms amplification (about 3.5e-7)."""
+    for kern in ("es", "kb"):
+        with pytest.raises(mm.MMError, match="status 3"):
+            mm.plan_query(2700, kern, 1e-6, "mixed", {"sigma": 1.25})
+        with pytest.raises(mm.MMError, match="status 3"):
+            mm.plan_query(2700, kern, 1e-12, "fp64", {"sigma": 1.25})
+    p = mm.plan_query(50_000, "es", 1e-6, "mixed", {"sigma": 1.55})
+    assert p["width"] == 9 and 3e-7 < p["est_err"] <= 1e-6
+    # explicit widths bypass the search, and the estimate then reports the floor
+    q = mm.plan_query(2700, "es", 1e-6, "mixed", {"sigma": 1.25, "width": 12})
+    assert q["est_err"] > 2e-6
+
+
 def test_fp64_default_is_paper_rule():
     for kern, tol in (("es", 1e-12), ("kb", 1e-9), ("g", 1e-6)):
         a = mm.plan_query(1000, kern, tol, "fp64")
