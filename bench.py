@@ -66,12 +66,12 @@ PROFILE_TRAFFIC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "prof
 def source_hash() -> str:
     """First 16 hex digits of the SHA-256 over the library's kernel sources and
     the tuned plan the default run uses."""
-    import glob
     import hashlib
+
+    from paper_2003_02842_amd.build import CSRC, HEADERS, SOURCES
     h = hashlib.sha256()
-    here = os.path.dirname(os.path.abspath(__file__))
-    for f in sorted(glob.glob(os.path.join(here, "paper_2003_02842_amd", "csrc", "*"))):
-        with open(f, "rb") as fh:
+    for f in sorted(SOURCES + HEADERS):
+        with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(fh.read())
     from paper_2003_02842_amd.tune import LARGE_UNIVERSE
     h.update(repr(sorted(LARGE_UNIVERSE.items())).encode())
@@ -110,8 +110,9 @@ def copy_calibration():
 
 
 def measured_peaks():
-    """Reference rates on this device: a 2 GiB device-to-device copy (HBM GB/s,
-    bytes read + written) and a 8192^3 BF16 library GEMM (TFLOP/s), best of 5."""
+    """Reference rates on this device, best of 5: a 2 GiB device-to-device copy
+    (HBM GB/s, bytes read + written), an 8192^3 BF16 library GEMM (TFLOP/s) and
+    a loop of back-to-back BF16 MFMAs with no memory traffic (TFLOP/s)."""
     import torch
     n = 2 << 30
     src = torch.empty(n, dtype=torch.uint8, device="cuda")
@@ -135,7 +136,22 @@ def measured_peaks():
     copy_ms = best(lambda: dst.copy_(src))
     gemm_ms = best(lambda: torch.mm(a, b))
     out = {"hbm_copy_gbs": 2 * n / (copy_ms * 1e-3) / 1e9, "bf16_gemm_tflops": 2 * 8192 ** 3 / (gemm_ms * 1e-3) / 1e12}
-    del src, dst, a, b
+    # BF16 MFMA issue rate with no memory traffic (libmm_peak.so): 1024 workgroups
+    # of four waves, each wave 8 x iters MFMAs of 32 x 32 x 16
+    import ctypes
+    peak = ctypes.CDLL(os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2003_02842_amd", "libmm_peak.so"))
+    peak.mm_peak_mfma_bf16.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+    blocks, iters = 1024, 4000
+    sink = torch.empty(blocks * 256, device="cuda")
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def mfma_loop():
+        if peak.mm_peak_mfma_bf16(blocks, iters, ctypes.c_void_p(sink.data_ptr()), stream) != 0:
+            raise RuntimeError("MFMA peak probe failed to launch")
+
+    mfma_ms = best(mfma_loop)
+    out["bf16_mfma_loop_tflops"] = blocks * 4 * iters * 8 * 32768 / (mfma_ms * 1e-3) / 1e12
+    del src, dst, a, b, sink
     torch.cuda.empty_cache()
     return out
 

@@ -4,7 +4,8 @@
 
 Every HIP source is compiled for gfx950 only, with packed-FP32 instruction
 selection disabled, and linked with the host runtime into one shared library
-next to this file.
+next to this file; the MFMA peak probe that bench.py runs goes into a library
+of its own (libmm_peak.so).
 """
 from __future__ import annotations
 
@@ -21,6 +22,10 @@ LIB = os.path.join(HERE, "libmm.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["mm_plan.cpp", "mm_api.cpp", "mm_nufft.hip", "mm_fft.hip", "mm_cov.hip", "mm_input.hip"]
+HEADERS = ["mm_internal.h"]
+# measurement probe for bench.py (not part of the estimator), its own library
+PEAK_SOURCE = "mm_peak.hip"
+PEAK_LIB = os.path.join(HERE, "libmm_peak.so")
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include")]
 DEVICE = ["-x", "hip", "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
@@ -48,8 +53,15 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError("link failed: %s\n%s\n%s" % (" ".join(cmd), r.stdout, r.stderr))
     os.replace(tmp, LIB)
+    peak_obj = _compile(PEAK_SOURCE)
+    tmp = PEAK_LIB + ".tmp%d" % os.getpid()
+    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp, peak_obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("link failed: %s\n%s\n%s" % (" ".join(cmd), r.stdout, r.stderr))
+    os.replace(tmp, PEAK_LIB)
     if verbose:
-        print("built", LIB)
+        print("built", LIB, PEAK_LIB)
     return LIB
 
 

@@ -20,3 +20,10 @@ def test_unknown_workload_is_rejected():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--workload", "no-such-workload"], capture_output=True, text=True,
                        timeout=120)
     assert r.returncode == 2 and "invalid choice" in r.stderr
+
+
+def test_mfma_peak_probe_is_built():
+    """bench.py's measured MFMA ceiling comes from libmm_peak.so (no GPU call here)."""
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2003_02842_amd", "libmm_peak.so"))
+    assert hasattr(lib, "mm_peak_mfma_bf16")
