@@ -111,8 +111,9 @@ def copy_calibration():
 
 def measured_peaks():
     """Reference rates on this device, best of 5: a 2 GiB device-to-device copy
-    (HBM GB/s, bytes read + written), an 8192^3 BF16 library GEMM (TFLOP/s) and
-    a loop of back-to-back BF16 MFMAs with no memory traffic (TFLOP/s)."""
+    by torch and by a plain float4 kernel (HBM GB/s, bytes read + written), an
+    8192^3 BF16 library GEMM (TFLOP/s) and a loop of back-to-back BF16 MFMAs with
+    no memory traffic (TFLOP/s)."""
     import torch
     n = 2 << 30
     src = torch.empty(n, dtype=torch.uint8, device="cuda")
@@ -151,6 +152,16 @@ def measured_peaks():
 
     mfma_ms = best(mfma_loop)
     out["bf16_mfma_loop_tflops"] = blocks * 4 * iters * 8 * 32768 / (mfma_ms * 1e-3) / 1e12
+    # the same 2 GiB copy with a plain float4 kernel, 2048 workgroups
+    peak.mm_peak_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p]
+
+    def kcopy():
+        if peak.mm_peak_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), n // 16, 2048,
+                             stream) != 0:
+            raise RuntimeError("copy probe failed to launch")
+
+    kcopy_ms = best(kcopy)
+    out["hbm_copy_kernel_gbs"] = 2 * n / (kcopy_ms * 1e-3) / 1e9
     del src, dst, a, b, sink
     torch.cuda.empty_cache()
     return out
