@@ -168,7 +168,11 @@ mm_status mm_estimate_workspace_size(int32_t G, int32_t D, const int32_t* Ns, in
  * (Sec. 2.2, equation defining F(dp_i)(k)); Monte Carlo replicates are the G
  * groups (Sec. 3).
  *   coef     optional S x ldc output of the coefficients (ldc >= max(Ns)+1); NULL keeps
- *            them in ws.
+ *            them in ws.  With NULL, G = 1, one cutoff and D on the MFMA path (mixed,
+ *            D(D+1)/2 > 1024, two-pass FFT), the coefficients are not stored at all:
+ *            the FFT's row pass writes the contraction's split BF16 operands itself,
+ *            rounded exactly as the split step would, so the results equal the
+ *            two-call form bit for bit.
  *   cov, corr  as mm_cov (corr may be NULL).
  *   ws       device workspace of at least mm_estimate_workspace_size bytes (256-byte aligned).
  *   use_graph 1: the first call with a given set of arguments (every pointer, size,

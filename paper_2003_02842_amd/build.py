@@ -22,7 +22,7 @@ LIB = os.path.join(HERE, "libmm.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["mm_plan.cpp", "mm_api.cpp", "mm_nufft.hip", "mm_fft.hip", "mm_cov.hip", "mm_input.hip"]
-HEADERS = ["mm_internal.h"]
+HEADERS = ["mm_bf16.h", "mm_internal.h"]
 # measurement probe for bench.py (not part of the estimator), its own library
 PEAK_SOURCE = "mm_peak.hip"
 PEAK_LIB = os.path.join(HERE, "libmm_peak.so")

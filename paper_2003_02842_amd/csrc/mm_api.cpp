@@ -89,14 +89,16 @@ static mm_status hip_status(hipError_t e) { return e == hipSuccess ? MM_OK : MM_
 // Tables, then the NUFFT of all S series (host checks already done).
 static hipError_t enqueue_nufft(const Plan& p, const NufftWs& w, char* wsb, int32_t S, const int64_t* offsets,
                                 const double* t, const void* dp, int32_t dp_is_fp64, double t0, double T,
-                                void* coef, int64_t ldc, hipStream_t st)
+                                void* coef, int64_t ldc, hipStream_t st, const SplitOut* so = nullptr)
 {
     hipError_t e = launch_prep(p, w, wsb, st);
     if (e != hipSuccess) return e;
     if (p.prec == MM_MIXED) {
-        if (p.fused) return launch_nufft_fused(p, w, wsb, S, offsets, t, dp, dp_is_fp64, t0, T, coef, ldc, st);
-        return launch_nufft_tiled(p, w, wsb, 0, S, offsets, t, dp, dp_is_fp64, t0, T, coef, ldc, st);
+        if (p.fused) return so ? hipErrorInvalidValue
+                               : launch_nufft_fused(p, w, wsb, S, offsets, t, dp, dp_is_fp64, t0, T, coef, ldc, st);
+        return launch_nufft_tiled(p, w, wsb, 0, S, offsets, t, dp, dp_is_fp64, t0, T, coef, ldc, st, so);
     }
+    if (so) return hipErrorInvalidValue;
     // plain form: one launch chain per series, grid buffer reused in stream order
     for (int32_t sidx = 0; sidx < S && e == hipSuccess; ++sidx)
         e = launch_nufft_tiled(p, w, wsb, sidx, 1, offsets, t, dp, dp_is_fp64, t0, T, coef, ldc, st);
@@ -108,7 +110,7 @@ static int small_d_limit(int32_t D) { return (int64_t)D * (D + 1) / 2 <= 1024; }
 // The contraction for every cutoff, then the correlation (host checks already done).
 static hipError_t enqueue_cov(int32_t G, int32_t D, const void* coef, int64_t ldc, const int32_t* Ns, int32_t nN,
                               int32_t Nmax, mm_basis basis, mm_prec prec, void* cov, void* corr, char* ws,
-                              hipStream_t st)
+                              hipStream_t st, bool operands_ready = false)
 {
     hipError_t e = hipSuccess;
     const size_t es = prec == MM_MIXED ? 4 : 8;
@@ -121,7 +123,7 @@ static hipError_t enqueue_cov(int32_t G, int32_t D, const void* coef, int64_t ld
         for (int q = 0; q < nN && e == hipSuccess; ++q) {
             char* cq = (char*)cov + (size_t)q * G * D * D * es;
             if (prec == MM_MIXED)
-                e = launch_cov_mfma(G, D, coef, ldc, Ns[q], basis, cq, ws, st);
+                e = launch_cov_mfma(G, D, coef, ldc, Ns[q], basis, cq, ws, st, operands_ready);
             else
                 e = launch_cov_fp64(G, D, coef, ldc, Ns[q], basis, cq, st);
         }
@@ -320,16 +322,29 @@ mm_status mm_estimate(int32_t G, int32_t D, const int64_t* offsets, const double
     if (!ws || ws_bytes < L.total) return MM_ERR_WORKSPACE;
     if (((uintptr_t)ws & 255) != 0) return MM_ERR_ARG;
     char* wsb = (char*)ws;
+    const bool coef_out = coef != nullptr;
     if (!coef) {
         coef = wsb + L.coef;
         ldc = (int64_t)Nmax + 1;
     }
     const NufftWs w = nufft_workspace(p, S);
     hipStream_t st = (hipStream_t)stream;
+    // With no coefficient output, one group and one cutoff on the MFMA path, the
+    // FFT's row pass writes the contraction's BF16 operands directly (the same
+    // values, rounded the same way, as the split step would).
+    const bool fuse = !coef_out && G == 1 && nN == 1 && prec == MM_MIXED && !p.fused && p.fft_ab &&
+                      !small_d_limit(D);
+    const SplitOut so = fuse ? cov_mfma_split_out(D, Ns[0], wsb + L.cov) : SplitOut{nullptr, nullptr, 0, nullptr};
     auto enqueue = [&]() -> hipError_t {
-        hipError_t e = enqueue_nufft(p, w, wsb + L.nufft, S, offsets, t, dp, dp_is_fp64, t0, T, coef, ldc, st);
+        hipError_t e = hipSuccess;
+        if (fuse) {
+            e = launch_split_prologue(D, Ns[0], basis, wsb + L.cov, st);
+            if (e != hipSuccess) return e;
+        }
+        e = enqueue_nufft(p, w, wsb + L.nufft, S, offsets, t, dp, dp_is_fp64, t0, T, coef, ldc, st,
+                          fuse ? &so : nullptr);
         if (e != hipSuccess) return e;
-        return enqueue_cov(G, D, coef, ldc, Ns, nN, Nmax, basis, prec, cov, corr, wsb + L.cov, st);
+        return enqueue_cov(G, D, coef, ldc, Ns, nN, Nmax, basis, prec, cov, corr, wsb + L.cov, st, fuse);
     };
     if (!use_graph) return hip_status(enqueue());
 
@@ -338,6 +353,7 @@ mm_status mm_estimate(int32_t G, int32_t D, const int64_t* offsets, const double
     put(key, G); put(key, D); put(key, dp_is_fp64); put(key, t0); put(key, T); put(key, nN);
     key.append(reinterpret_cast<const char*>(Ns), sizeof(int32_t) * (size_t)nN);
     put(key, basis); put(key, kernel); put(key, tol); put(key, prec); put(key, ldc); put(key, ws_bytes);
+    put(key, coef_out);
     put(key, ptrs);
     const mm_tuning tz = tune ? *tune : mm_tuning{0, 0.0, 0, 0, 0.0, 0, 0};
     put(key, tz.width); put(key, tz.sigma); put(key, tz.tile); put(key, tz.fused); put(key, tz.es_beta_per_tap);

@@ -20,6 +20,7 @@
 //   k_corr          R_ij = Sigma_ij / sqrt(Sigma_ii Sigma_jj), NaN if a variance <= 0
 #include <hip/hip_runtime.h>
 
+#include "mm_bf16.h"
 #include "mm_internal.h"
 
 namespace mm {
@@ -217,14 +218,6 @@ constexpr int ST = 128;         // output tile edge
 constexpr int SK = 32;          // k (real columns) per LDS stage
 constexpr int SLD = SK + 8;     // padded LDS row, bf16 elements
 
-__device__ __forceinline__ uint16_t bf16_rne(float x)
-{
-    uint32_t u = __float_as_uint(x);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
-
-__device__ __forceinline__ float bf16_to_f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 // X (Dp x Kp, zero padded) from float2 coefficients: column 2k+e = s_k (Re, Im)_e c_k.
 // Column scale of X: s_k = 2pi sqrt(m_k w_k) for k <= N (FP64, rounded once), 0 on
@@ -249,17 +242,17 @@ __global__ void k_split_bf16(int D, const float2* __restrict__ coef, int64_t ldc
 {
     const int64_t row = blockIdx.y;
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < Kp / 2; c += (int64_t)gridDim.x * blockDim.x) {
-        float2 v = make_float2(0.f, 0.f);
+        float2 cc = make_float2(0.f, 0.f);
+        float sc = 0.f;
         const int k = (int)c;
         if (row < D && k <= N) {
-            const float sc = scale[k];
-            const float2 cc = coef[row * ldc + k];
-            v = make_float2(cc.x * sc, cc.y * sc);
+            sc = scale[k];
+            cc = coef[row * ldc + k];
         }
-        uint16_t h0 = bf16_rne(v.x), h1 = bf16_rne(v.y);
-        uint16_t l0 = bf16_rne(v.x - bf16_to_f(h0)), l1 = bf16_rne(v.y - bf16_to_f(h1));
-        *(uint32_t*)&hi[row * Kp + 2 * c] = (uint32_t)h0 | ((uint32_t)h1 << 16);
-        *(uint32_t*)&lo[row * Kp + 2 * c] = (uint32_t)l0 | ((uint32_t)l1 << 16);
+        uint32_t h, l;
+        bf16_split_pair(cc.x, cc.y, sc, h, l);
+        *(uint32_t*)&hi[row * Kp + 2 * c] = h;
+        *(uint32_t*)&lo[row * Kp + 2 * c] = l;
     }
 }
 
@@ -768,25 +761,72 @@ size_t cov_mfma_workspace(int32_t G, int32_t D, int32_t Nmax)
     return mfma_shape(D, Nmax).total;
 }
 
+// Zero padding of the split operands when the row pass writes them: the pairs
+// beyond N of rows below D (tail = kp2 - N - 1 each), then rows D..Dp-1 whole,
+// as one grid-stride range.
+__global__ void k_split_pad(int D, int Dp, int N, int64_t kp2, uint32_t* __restrict__ hi, uint32_t* __restrict__ lo)
+{
+    const int64_t tail = kp2 - N - 1;
+    const int64_t n1 = (int64_t)D * tail, total = n1 + (int64_t)(Dp - D) * kp2;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t at = i < n1 ? (i / tail) * kp2 + (N + 1) + i % tail : (int64_t)D * kp2 + (i - n1);
+        hi[at] = 0u;
+        lo[at] = 0u;
+    }
+}
+
+SplitOut cov_mfma_split_out(int32_t D, int32_t N, char* ws)
+{
+    const MfmaShape s = mfma_shape(D, N);
+    SplitOut o;
+    o.hi = (uint32_t*)(ws + s.hi);
+    o.lo = (uint32_t*)(ws + s.lo);
+    o.kp2 = s.Kp / 2;
+    o.scale = (const float*)(ws + s.scale);
+    return o;
+}
+
+hipError_t launch_split_prologue(int32_t D, int32_t N, int basis, char* ws, hipStream_t st)
+{
+    const MfmaShape s = mfma_shape(D, N);
+    prof_begin("k_split_scale", st);
+    hipLaunchKernelGGL(k_split_scale, dim3((unsigned)((s.Kp / 2 + 255) / 256)), dim3(256), 0, st, N, basis, s.Kp / 2,
+                       (float*)(ws + s.scale));
+    prof_end("k_split_scale", st);
+    const int64_t kp2 = s.Kp / 2;
+    const int64_t total = (int64_t)D * (kp2 - N - 1) + (s.Dp - D) * kp2;
+    const int bx = (int)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 1024));
+    prof_begin("k_split_pad", st);
+    hipLaunchKernelGGL(k_split_pad, dim3(bx), dim3(256), 0, st, D, (int)s.Dp, N, kp2, (uint32_t*)(ws + s.hi),
+                       (uint32_t*)(ws + s.lo));
+    prof_end("k_split_pad", st);
+    return hipGetLastError();
+}
+
 hipError_t launch_cov_mfma(int32_t G, int32_t D, const void* coef, int64_t ldc, int32_t N, int basis, void* cov,
-                           char* ws, hipStream_t st)
+                           char* ws, hipStream_t st, bool operands_ready)
 {
     MfmaShape s = mfma_shape(D, N);
     uint16_t* hi = (uint16_t*)(ws + s.hi);
     uint16_t* lo = (uint16_t*)(ws + s.lo);
     float* part = (float*)(ws + s.partial);
     float* scale = (float*)(ws + s.scale);
-    prof_begin("k_split_scale", st);
-    hipLaunchKernelGGL(k_split_scale, dim3((unsigned)((s.Kp / 2 + 255) / 256)), dim3(256), 0, st, N, basis, s.Kp / 2,
-                       scale);
-    prof_end("k_split_scale", st);
+    if (operands_ready && G != 1) return hipErrorInvalidValue;
+    if (!operands_ready) {
+        prof_begin("k_split_scale", st);
+        hipLaunchKernelGGL(k_split_scale, dim3((unsigned)((s.Kp / 2 + 255) / 256)), dim3(256), 0, st, N, basis,
+                           s.Kp / 2, scale);
+        prof_end("k_split_scale", st);
+    }
     for (int g = 0; g < G; ++g) {
         const float2* cg = (const float2*)coef + (int64_t)g * D * ldc;
         int bx = (int)std::min<int64_t>((s.Kp / 2 + 255) / 256, 64);
-        prof_begin("k_split_bf16", st);
-        hipLaunchKernelGGL(k_split_bf16, dim3(bx, s.Dp), dim3(256), 0, st, D, cg, ldc, N, (const float*)scale, s.Kp,
-                           hi, lo);
-        prof_end("k_split_bf16", st);
+        if (!operands_ready) {
+            prof_begin("k_split_bf16", st);
+            hipLaunchKernelGGL(k_split_bf16, dim3(bx, s.Dp), dim3(256), 0, st, D, cg, ldc, N, (const float*)scale,
+                               s.Kp, hi, lo);
+            prof_end("k_split_bf16", st);
+        }
         const char* syrk_name = s.ts == T2 ? "k_syrk_mfma256" : "k_syrk_mfma";
         prof_begin(syrk_name, st);
         if (s.ts == T2)

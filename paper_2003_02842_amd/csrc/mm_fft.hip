@@ -21,6 +21,7 @@
 // halves (about 2 sqrt(L) entries) sit in LDS.
 #include <hip/hip_runtime.h>
 
+#include "mm_bf16.h"
 #include "mm_internal.h"
 
 #ifndef MM_FFT_ROWS_XCD
@@ -323,7 +324,8 @@ __global__ __launch_bounds__(512) void k_fft_rows_ab(const T* __restrict__ grid,
                                                      const typename CTf<T>::type* __restrict__ log_,
                                                      const typename CTf<T>::type* __restrict__ hig, int lo_bits,
                                                      int n_hi, const T* __restrict__ dfac, int N,
-                                                     typename CTf<T>::type* __restrict__ coef, int64_t ldc, int s_out)
+                                                     typename CTf<T>::type* __restrict__ coef, int64_t ldc, int s_out,
+                                                     SplitOut so)
 {
     using C = typename CTf<T>::type;
     extern __shared__ __align__(16) char smem_raw[];
@@ -413,7 +415,21 @@ __global__ __launch_bounds__(512) void k_fft_rows_ab(const T* __restrict__ grid,
         const C Bv = C{Zk.x - Zm.x, Zk.y + Zm.y};
         const C WB = cmulf(tw_split(lo, hi, (int)k, lo_bits), Bv);
         const T d = dfac[k] * (T)0.5;
-        out[k] = C{(Av.x + WB.y) * d, (Av.y - WB.x) * d};
+        C ck = C{(Av.x + WB.y) * d, (Av.y - WB.x) * d};
+        // one value for both outputs: the coefficient and its split must agree bit for bit
+        asm volatile("" : "+v"(ck.x), "+v"(ck.y));
+        if constexpr (sizeof(T) == 4) {
+            if (so.hi) {
+                // the split step fused: X = s_k c_k as BF16 hi and lo, rounded as k_split_bf16 does
+                uint32_t h, l;
+                bf16_split_pair(ck.x, ck.y, so.scale[k], h, l);
+                const int64_t at = (int64_t)(s_out + by) * so.kp2 + k;
+                so.hi[at] = h;
+                so.lo[at] = l;
+                continue;
+            }
+        }
+        out[k] = ck;
     }
 }
 
@@ -474,8 +490,9 @@ static int round64(int x) { return (x + 63) & ~63; }
 
 template <typename T>
 static hipError_t fft_ab_t(const Plan& p, const NufftWs& w, char* ws, int32_t s_begin, int32_t s_count, T* grid,
-                           int64_t gstride, void* coef, int64_t ldc, hipStream_t st)
+                           int64_t gstride, void* coef, int64_t ldc, hipStream_t st, const SplitOut* so)
 {
+    const SplitOut none{nullptr, nullptr, 0, nullptr};
     using C = typename CTf<T>::type;
     const int t1 = round64(p.CC * std::max(p.A1, p.B1));
     prof_begin("k_fft_cols_ab", st);
@@ -489,17 +506,18 @@ static hipError_t fft_ab_t(const Plan& p, const NufftWs& w, char* ws, int32_t s_
     hipLaunchKernelGGL(k_fft_rows_ab<T>, dim3((P + p.RR - 1) / p.RR, s_count), dim3(t2), fft_ab_lds_rows(p), st,
                        grid, gstride, p.L1, p.L2, p.L2p, p.A2, p.B2, p.RR, (const C*)(ws + w.tw2),
                        (const C*)(ws + w.tMlo), (const C*)(ws + w.tMhi), p.tw_lo_bits, p.tw_hi_M,
-                       (const T*)(ws + w.dfac), p.N, (C*)coef, ldc, s_begin);
+                       (const T*)(ws + w.dfac), p.N, (C*)coef, ldc, s_begin, so ? *so : none);
     prof_end("k_fft_rows_ab", st);
     return hipGetLastError();
 }
 
 hipError_t launch_fft_ab(const Plan& p, const NufftWs& w, char* ws, int32_t s_begin, int32_t s_count, void* grid,
-                         int64_t gstride, void* coef, int64_t ldc, hipStream_t st)
+                         int64_t gstride, void* coef, int64_t ldc, hipStream_t st, const SplitOut* so)
 {
     if (p.prec == MM_MIXED)
-        return fft_ab_t<float>(p, w, ws, s_begin, s_count, (float*)grid, gstride, coef, ldc, st);
-    return fft_ab_t<double>(p, w, ws, s_begin, s_count, (double*)grid, gstride, coef, ldc, st);
+        return fft_ab_t<float>(p, w, ws, s_begin, s_count, (float*)grid, gstride, coef, ldc, st, so);
+    if (so) return hipErrorInvalidValue;
+    return fft_ab_t<double>(p, w, ws, s_begin, s_count, (double*)grid, gstride, coef, ldc, st, nullptr);
 }
 
 hipError_t launch_fft_ab_tables(const Plan& p, const NufftWs& w, char* ws, hipStream_t st)

@@ -123,9 +123,21 @@ hipError_t ensure_constants(int device);
 hipError_t launch_prep(const Plan& p, const NufftWs& w, char* ws, hipStream_t st);
 hipError_t launch_validate(int32_t S, const int64_t* offsets, const double* t, const void* dp, int dp_fp64,
                            double t0, double T, int* flag, hipStream_t st);
+// Destination of the split fused into the FFT's row pass: X = s_k c_k written as
+// BF16 hi and lo parts in the layout of the MFMA contraction's operands (row =
+// series, uint32 pair (Re, Im) at column k) instead of the coefficients c_k.
+struct SplitOut {
+    uint32_t* hi;
+    uint32_t* lo;
+    int64_t kp2;           // pairs per row (Kp / 2)
+    const float* scale;    // s_k, zero beyond N
+};
+
+
 hipError_t launch_nufft_tiled(const Plan& p, const NufftWs& w, char* ws, int32_t s_begin, int32_t s_count,
                               const int64_t* offsets, const double* t, const void* dp, int dp_fp64,
-                              double t0, double T, void* coef, int64_t ldc, hipStream_t st);
+                              double t0, double T, void* coef, int64_t ldc, hipStream_t st,
+                              const SplitOut* so = nullptr);
 hipError_t launch_spread_poly(const Plan& p, int s_count, const double* t, const void* dp, int dp_fp64, double t0,
                               double t_end, const int64_t* ranges, int tiles, float* grid, int64_t grid_stride,
                               hipStream_t st);
@@ -139,7 +151,7 @@ size_t fft_ab_lds_cols(const Plan& p);
 size_t fft_ab_lds_rows(const Plan& p);
 hipError_t launch_fft_ab_tables(const Plan& p, const NufftWs& w, char* ws, hipStream_t st);
 hipError_t launch_fft_ab(const Plan& p, const NufftWs& w, char* ws, int32_t s_begin, int32_t s_count, void* grid,
-                         int64_t gstride, void* coef, int64_t ldc, hipStream_t st);
+                         int64_t gstride, void* coef, int64_t ldc, hipStream_t st, const SplitOut* so = nullptr);
 
 // Paper-form input (mm_input.hip): price/time matrices to CSR returns.
 struct InputWs {
@@ -163,8 +175,15 @@ hipError_t launch_corr(int prec, int64_t mats, int32_t D, const void* cov, void*
 size_t cov_mfma_workspace(int32_t G, int32_t D, int32_t Nmax);
 hipError_t launch_pairwise_select(int prec, int32_t G, int32_t D, const int32_t* qidx, const void* sweep, void* cov,
                                   void* corr, hipStream_t st);
+// operands_ready: the split operands were written by the NUFFT's row pass
+// (launch_split_prologue, then SplitOut), so the scale and split steps are skipped.
 hipError_t launch_cov_mfma(int32_t G, int32_t D, const void* coef, int64_t ldc, int32_t N, int basis,
-                           void* cov, char* ws, hipStream_t st);
+                           void* cov, char* ws, hipStream_t st, bool operands_ready = false);
+// The fused split for one group and one cutoff N of the MFMA contraction: the
+// operand pointers in its workspace, and a prologue that writes the column scale
+// table and zeroes the operands' padding (rows D..Dp-1, columns beyond N).
+SplitOut cov_mfma_split_out(int32_t D, int32_t N, char* ws);
+hipError_t launch_split_prologue(int32_t D, int32_t N, int basis, char* ws, hipStream_t st);
 hipError_t launch_cov_fp64(int32_t G, int32_t D, const void* coef, int64_t ldc, int32_t N, int basis,
                            void* cov, hipStream_t st);
 

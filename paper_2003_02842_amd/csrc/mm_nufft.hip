@@ -1116,7 +1116,7 @@ static int ilog2(int x)
 template <typename T>
 static hipError_t nufft_tiled_t(const Plan& p, const NufftWs& w, char* ws, int32_t s_begin, int32_t s_count,
                                 const int64_t* offsets, const double* t, const void* dp, int dp_fp64, double t0,
-                                double T_, void* coef, int64_t ldc, hipStream_t st)
+                                double T_, void* coef, int64_t ldc, hipStream_t st, const SplitOut* so)
 {
     using C = typename CT<T>::type;
     T* grid = (T*)(ws + w.grid);
@@ -1153,7 +1153,8 @@ static hipError_t nufft_tiled_t(const Plan& p, const NufftWs& w, char* ws, int32
     }
     prof_end(spread_name, st);
 
-    if (p.fft_ab) return launch_fft_ab(p, w, ws, s_begin, s_count, grid, gstride, coef, ldc, st);
+    if (p.fft_ab) return launch_fft_ab(p, w, ws, s_begin, s_count, grid, gstride, coef, ldc, st, so);
+    if (so) return hipErrorInvalidValue;   // the split is fused only into the two-pass FFT
     const int cbs = ilog2(p.CB);
     const size_t lds1 = (size_t)(p.L1 + p.CB * (p.L1 | 1)) * sizeof(C) + (size_t)((p.L1 + 3) & ~3) * 4;
     prof_begin("k_fft_cols", st);
@@ -1175,12 +1176,13 @@ static hipError_t nufft_tiled_t(const Plan& p, const NufftWs& w, char* ws, int32
 
 hipError_t launch_nufft_tiled(const Plan& p, const NufftWs& w, char* ws, int32_t s_begin, int32_t s_count,
                               const int64_t* offsets, const double* t, const void* dp, int dp_fp64, double t0,
-                              double T, void* coef, int64_t ldc, hipStream_t st)
+                              double T, void* coef, int64_t ldc, hipStream_t st, const SplitOut* so)
 {
     if (s_count <= 0) return hipSuccess;
     if (p.prec == MM_MIXED)
-        return nufft_tiled_t<float>(p, w, ws, s_begin, s_count, offsets, t, dp, dp_fp64, t0, T, coef, ldc, st);
-    return nufft_tiled_t<double>(p, w, ws, s_begin, s_count, offsets, t, dp, dp_fp64, t0, T, coef, ldc, st);
+        return nufft_tiled_t<float>(p, w, ws, s_begin, s_count, offsets, t, dp, dp_fp64, t0, T, coef, ldc, st, so);
+    if (so) return hipErrorInvalidValue;
+    return nufft_tiled_t<double>(p, w, ws, s_begin, s_count, offsets, t, dp, dp_fp64, t0, T, coef, ldc, st, nullptr);
 }
 
 hipError_t launch_nufft_fused(const Plan&, const NufftWs&, char*, int32_t, const int64_t*, const double*,

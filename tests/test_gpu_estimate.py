@@ -118,3 +118,37 @@ def test_graph_with_coefficient_output_and_new_cutoffs(mm):
         results.append(S)
     assert same(results[0], results[2])
     mm.graph_cache_clear()
+
+
+@pytest.mark.parametrize("basis", ["dirichlet", "fejer"])
+@pytest.mark.parametrize("D,tune", [(300, None), (1100, None), (1100, {"sigma": 1.55, "tile": 2048})])
+def test_fused_split_equals_two_calls(mm, basis, D, tune):
+    """With no coefficient output, one group and one cutoff on the MFMA path, the
+    FFT's row pass writes the contraction's BF16 operands itself; the operands,
+    hence Sigma and R, must equal the two-call form's bit for bit (128- and
+    256-wide SYRK tiles, a ragged last tile row, the tuned plan), eagerly and as
+    graph replays, and the oracle on a few series."""
+    w = synth.random_events(D, 50, 1500, seed=4040 + D, dp_dtype=torch.float32, device="cuda")
+    N = 3000
+    c = mm.nufft1(w.offsets, w.t, w.dp, w.t0, w.T, N, "es", 1e-6, "mixed", tune)
+    S1, R1 = mm.cov(c, 1, D, [N], basis)
+    S2, R2, ws = mm.estimate(w.offsets, w.t, w.dp, w.t0, w.T, 1, D, [N], basis, "es", 1e-6, "mixed", tune)
+    torch.cuda.synchronize()
+    assert same(S1, S2) and same(R1, R2)
+    out = (torch.empty_like(S2), torch.empty_like(R2))
+    st = torch.cuda.Stream()
+    for rep in range(3):
+        out[0].fill_(float("nan"))
+        st.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(st):
+            mm.estimate(w.offsets, w.t, w.dp, w.t0, w.T, 1, D, [N], basis, "es", 1e-6, "mixed", tune, use_graph=True,
+                        ws=ws, out=out)
+        st.synchronize()
+        assert same(S1, out[0]) and same(R1, out[1]), rep
+        torch.cuda.synchronize()
+    mm.graph_cache_clear()
+    # and against the oracle on the first four series (their block of Sigma and R)
+    sub = w.to("cpu").subset([0, 1, 2, 3])
+    b = oracle.DIRICHLET if basis == "dirichlet" else oracle.FEJER
+    So, Ro = oracle.cov(oracle.coeffs_batch(sub.offsets, sub.t, sub.dp, sub.t0, sub.T, N), 1, 4, [N], b)
+    assert relfro(S2[0, 0, :4, :4].cpu().numpy(), So[0, 0]) <= MIXED_BAR
