@@ -4,7 +4,8 @@
 One step = the whole path over one batch of synthetic input already resident in
 HBM: the type-1 NUFFT of every series (spreading, two-pass grid FFT,
 deconvolution) and the Fejer contraction with correlation, in the mixed form
-(FP32 NUFFT, split-BF16 MFMA contraction).
+(FP32 NUFFT, split-BF16 MFMA contraction), as one mm_estimate call with no
+coefficient output (the FFT's row pass writes the contraction's operands).
 
 Workload (default): the large-universe case -- D = 2000 assets of a 3-factor
 GBM, event counts log-uniform in [1e4, 1e6] (about 4.3e8 events), horizon
