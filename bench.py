@@ -212,9 +212,14 @@ def estimate_bench(a):
     ws = torch.empty(mm.estimate_workspace_size(G, D, Ns, kern, tol, "mixed"), dtype=torch.uint8, device="cuda")
     out = (torch.empty((len(Ns), G, D, D), device="cuda"), torch.empty((len(Ns), G, D, D), device="cuda"))
 
+    gst = torch.cuda.Stream()
+
     def graph_step():
-        mm.estimate(w.offsets, w.t, w.dp, w.t0, w.T, G, D, Ns, basis, kern, tol, "mixed", out=out, ws=ws,
-                    use_graph=True)
+        # replayed on a stream of its own: on torch's default stream the binding
+        # would hop to a side stream and back around every replay
+        with torch.cuda.stream(gst):
+            mm.estimate(w.offsets, w.t, w.dp, w.t0, w.T, G, D, Ns, basis, kern, tol, "mixed", out=out, ws=ws,
+                        use_graph=True)
 
     def eager_step():
         mm.estimate(w.offsets, w.t, w.dp, w.t0, w.T, G, D, Ns, basis, kern, tol, "mixed", out=out, ws=ws)
