@@ -44,6 +44,7 @@ def lib():
         P = ctypes.c_void_p
         i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
         L.orc_coeffs.argtypes = [i64, P, P, f64, f64, i64, i64, P]
+        L.orc_coeffs_at.argtypes = [i64, P, P, f64, f64, P, i64, P]
         L.orc_coeffs_batch.argtypes = [i32, P, P, P, f64, f64, i32, P, i64]
         L.orc_cov_full.argtypes = [i32, i32, P, i64, i32, i32, P, P, P]
         L.orc_cov.argtypes = [i32, i32, P, i64, P, i32, i32, P, P]
@@ -72,6 +73,16 @@ def coeffs(t, dp, t0: float, T: float, klo: int, khi: int) -> np.ndarray:
     dp = _np(dp, np.float64)
     out = np.zeros(2 * (khi - klo + 1), dtype=np.float64)
     lib().orc_coeffs(t.size, _p(t), _p(dp), t0, T, klo, khi, _p(out))
+    return out.view(np.complex128)
+
+
+def coeffs_at(t, dp, t0: float, T: float, ks) -> np.ndarray:
+    """c_k of one series at the listed frequencies ks (complex128, same order)."""
+    t = _np(t, np.float64)
+    dp = _np(dp, np.float64)
+    ks = np.ascontiguousarray(ks, dtype=np.int64)
+    out = np.zeros(2 * ks.size, dtype=np.float64)
+    lib().orc_coeffs_at(t.size, _p(t), _p(dp), t0, T, _p(ks), ks.size, _p(out))
     return out.view(np.complex128)
 
 

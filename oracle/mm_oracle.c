@@ -101,6 +101,18 @@ void orc_coeffs(int64_t n, const double* t, const double* dp, double t0, double 
     free(u);
 }
 
+/* c_k of one series of n events at the nk listed frequencies ks[] (any order). */
+void orc_coeffs_at(int64_t n, const double* t, const double* dp, double t0, double T,
+                   const int64_t* ks, int64_t nk, double* out)
+{
+    double* u = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    for (int64_t h = 0; h < n; ++h) u[h] = rescale(t[h], t0, T);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t j = 0; j < nk; ++j)
+        coeffs_series(n, u, dp, ks[j], &out[2 * j], &out[2 * j + 1]);
+    free(u);
+}
+
 /* S series in CSR form; coef is S x ldc complex (interleaved re,im), k = 0..N. */
 void orc_coeffs_batch(int32_t S, const int64_t* offsets, const double* t, const double* dp,
                       double t0, double T, int32_t N, double* coef, int64_t ldc)

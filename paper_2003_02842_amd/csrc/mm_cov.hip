@@ -143,12 +143,13 @@ __global__ void k_corr(int64_t total, int D, const OT* __restrict__ cov, OT* __r
 {
     int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= total) return;
-    int64_t DD = (int64_t)D * D;
-    int64_t m = idx / DD;
-    int r = (int)(idx - m * DD);
-    int i = r / D, j = r - i * D;
+    // 64-bit flat indices: D * D exceeds 2^31 once D > 46340
+    const int64_t DD = (int64_t)D * D;
+    const int64_t m = idx / DD;
+    const int64_t r = idx - m * DD;
+    const int64_t i = r / D, j = r - i * D;
     const OT* C = cov + m * DD;
-    OT a = C[i * D + i], b = C[j * D + j];
+    const OT a = C[i * D + i], b = C[j * D + j];
     corr[idx] = (a > (OT)0 && b > (OT)0) ? C[r] / (sqrt(a) * sqrt(b)) : (OT)NAN;
 }
 
@@ -574,17 +575,17 @@ __global__ void k_pairwise_select(int64_t total, int D, int G, const int32_t* __
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= total) return;
-    const int64_t DD = (int64_t)D * D;
+    const int64_t DD = (int64_t)D * D;   // 64-bit flat indices, as in k_corr
     const int64_t g = idx / DD;
-    const int r = (int)(idx - g * DD);
-    const int i = r / D, j = r - i * D;
+    const int64_t r = idx - g * DD;
+    const int64_t i = r / D, j = r - i * D;
     const int qi = qidx[i], qj = qidx[j];
     const int q = qi < qj ? qi : qj;     // slices ascend with the cutoff
     const OT* Sq = sweep + ((int64_t)q * G + g) * DD;
     const OT v = Sq[r];
     cov[idx] = v;
     if (corr) {
-        const OT a = Sq[(int64_t)i * D + i], b = Sq[(int64_t)j * D + j];
+        const OT a = Sq[i * D + i], b = Sq[j * D + j];
         corr[idx] = (a > (OT)0 && b > (OT)0) ? v / (sqrt(a) * sqrt(b)) : (OT)NAN;
     }
 }
@@ -742,7 +743,8 @@ static MfmaShape mfma_shape(int32_t D, int32_t N)
     int best_m = (int)((512 + 8ll * s.ntiles - 1) / (8ll * s.ntiles));
     const int max_m = (int)std::max<int64_t>(1, ksteps / 64);
     best_m = std::max(1, std::min(best_m, max_m));
-    s.nsplit = 8 * best_m;
+    // never more ranges than k-stages (an empty range would still write a partial tile)
+    s.nsplit = (int)std::min<int64_t>(8 * best_m, ksteps);
     int64_t per = (s.Kp + s.nsplit - 1) / s.nsplit;
     s.kchunk = ((per + SK - 1) / SK) * SK;
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };

@@ -101,7 +101,6 @@ struct Plan {
     PolyParams pp;
     int tile;            // cells per spreading tile: 1024, 2048 or 4096 (256 threads x 4, 8, 16 cells)
     int fused;           // 1: single-workgroup LDS-resident NUFFT per series
-    int fused_threads;
 };
 
 // Plan construction (host only, no device calls).  Returns MM_OK or an error.
@@ -119,7 +118,6 @@ struct NufftWs {
 NufftWs nufft_workspace(const Plan& p, int32_t S);
 
 // Launchers (mm_nufft.hip).  All asynchronous on `st`.
-hipError_t ensure_constants(int device);
 hipError_t launch_prep(const Plan& p, const NufftWs& w, char* ws, hipStream_t st);
 hipError_t launch_validate(int32_t S, const int64_t* offsets, const double* t, const void* dp, int dp_fp64,
                            double t0, double T, int* flag, hipStream_t st);

@@ -234,6 +234,7 @@ template <typename T>
 struct KEval {
     T inv_hw, es_c;        // ES: exp(beta (sqrt(1 - (x/hw)^2) - 1)); es_c = beta (log2 e for FP32)
     T g_c;                 // Gaussian: exp(-t1 x^2); g_c = t1 (times log2 e for FP32)
+    T g_off;               // Gaussian: 1 - hw, so that x = (j + g_off) - f
     T kb_m2, kb_b, kb_inv_norm;
     __device__ explicit KEval(const KernParams& kp)
     {
@@ -241,6 +242,7 @@ struct KEval {
         inv_hw = (T)kp.es_inv_hw;
         es_c = (T)(kp.es_beta * l2e);
         g_c = (T)(kp.g_t1 * l2e);
+        g_off = (T)(1.0 - kp.hw);
         kb_m2 = (T)(kp.kb_m * kp.kb_m);
         kb_b = (T)kp.kb_b;
         kb_inv_norm = (T)kp.kb_inv_norm;
@@ -323,26 +325,19 @@ __global__ void k_tile_ranges(const int64_t* __restrict__ offsets, const double*
 // One staged event.  key = first-tap cell relative to the tile plus w - 1 (a
 // small integer held exactly as a float); the tap at cell c has index
 // j = c + w - 1 - key and kernel argument x = j + x0 with x0 = 1 - f - hw.
-// a and b are per-event constants of the kernel in j:
+// a is a per-event constant of the kernel in j:
 //   ES  a = x0/hw           z = j/hw + a, value exp(beta (sqrt(1 - z^2) - 1))
-//   G   a = -t1 x0^2,       exponent a + j (b - t1 j) = -t1 (j + x0)^2
-//       b = -2 t1 x0        (FP32 forms scale t1 by log2 e for exp2)
+//   G   a = f               x = (j + 1 - hw) - f, value exp(-t1 x^2) (FP32: exp2 with
+//                           t1 log2 e); j + 1 - hw is exact, so x carries only the
+//                           rounding of f, and the exponent is not formed by
+//                           cancelling terms of size t1 x0^2
 //   KB  a = x0              x = j + a
-// The Gaussian needs both a and b (16-byte record); ES and KB only a (12 bytes),
-// which keeps more workgroups resident in LDS.
-template <typename T, bool HAS_B>
-struct EvRecT;
 template <typename T>
-struct EvRecT<T, true> {
-    T key, a, b, v;
-};
-template <typename T>
-struct EvRecT<T, false> {
+struct EvRec {
     T key, a, v;
-    static constexpr T b = (T)0;
 };
 template <typename T, int KIND>
-using EvRecK = EvRecT<T, KIND == MM_GAUSSIAN>;
+using EvRecK = EvRec<T>;
 
 template <typename T, int KIND>
 __device__ __forceinline__ EvRecK<T, KIND> make_rec(int key, double x0, T v, const KernParams& kp)
@@ -353,9 +348,7 @@ __device__ __forceinline__ EvRecK<T, KIND> make_rec(int key, double x0, T v, con
     if constexpr (KIND == MM_ES) {
         r.a = (T)(x0 * kp.es_inv_hw);
     } else if constexpr (KIND == MM_GAUSSIAN) {
-        const double c = kp.g_t1 * ((sizeof(T) == 4) ? 1.4426950408889634074 : 1.0);
-        r.a = (T)(-c * x0 * x0);
-        r.b = (T)(-2.0 * c * x0);
+        r.a = (T)(1.0 - kp.hw - x0);
     } else {
         r.a = (T)x0;
     }
@@ -376,9 +369,9 @@ __device__ __forceinline__ T pair_value(T j, const EvRecK<T, KIND>& r, const KEv
             return r.v * exp(fma(k.es_c, sqrt(q), -k.es_c));
         }
     } else if (KIND == MM_GAUSSIAN) {
-        const T e = fma(j, fma(j, -k.g_c, r.b), r.a);
-        if constexpr (sizeof(T) == 4) return r.v * fexp2(e);
-        else return r.v * exp(e);
+        const T x = (j + k.g_off) - r.a;
+        if constexpr (sizeof(T) == 4) return r.v * fexp2(-k.g_c * x * x);
+        else return r.v * exp(-k.g_c * x * x);
     } else {
         return r.v * kern_eval<T, MM_KAISER_BESSEL>(j + r.a, k);
     }
@@ -581,16 +574,18 @@ __global__ __launch_bounds__(256) void k_spread_poly(const double* __restrict__ 
     auto chunk = [&](int q, double (&tv)[SB], DPT (&dv)[SB]) {
         int64_t cb; int n, m;
         locate(q, cb, n, m);
-        const int64_t shift = (int64_t)a + (int64_t)(m - 1) * Mr;
+        // key = first-tap cell - (a + (m - 1) Mr) + W - 1, the first-tap cell being floor(g - hw) + 1
+        const int kofs = (int)((int64_t)W - (int64_t)a - (int64_t)(m - 1) * Mr);
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < SB; ++u) {
             const int i = (int)threadIdx.x + 256 * u;
             if (i < n) {
-                int64_t l0;
-                double f;
-                cell_of<false>(tv[u], t0, span, scale, Mr, hw, l0, f);
-                const int key = (int)(l0 - shift) + W - 1;   // >= 0; tap j reaches cell key - W + 1 + j
+                // cell_of<false> with the cell in 32 bits (|floor(g - hw)| < Mr + w < 2^31)
+                const double tt = fma(__dsub_rn(tv[u], t0), scale, -hw);
+                const double fl = floor(tt);
+                const double f = __dsub_rn(tt, fl);
+                const int key = (int)fl + kofs;              // >= 0; tap j reaches cell key - W + 1 + j
                 const float sv = (float)(f - 0.5);
                 const float v = (float)dv[u];
                 // tap j = v (E_j(s^2) + s O_j(s^2)) and, by the kernel's symmetry, tap W-1-j =
@@ -1026,16 +1021,13 @@ __global__ void k_validate(int32_t S, const int64_t* __restrict__ offsets, const
 
 static GLRule host_gl()
 {
-    static GLRule g;
-    static bool done = false;
-    if (!done) {
-        gauss_legendre_pos(kGLNodes, g.x, g.w);
-        done = true;
-    }
-    return g;
+    struct Rule {
+        GLRule g;
+        Rule() { gauss_legendre_pos(kGLNodes, g.x, g.w); }
+    };
+    static const Rule rule;   // built once, thread-safe (C++11 function-local static)
+    return rule.g;
 }
-
-hipError_t ensure_constants(int) { return hipSuccess; }
 
 hipError_t launch_prep(const Plan& p, const NufftWs& w, char* ws, hipStream_t st)
 {

@@ -211,9 +211,13 @@ static double host_i0(double x)
 // support: 2 int_0^hw psi(x) cos(2 pi nu x) dx, composite 16-point Gauss-Legendre.
 static double host_psihat_trunc(const KernParams& kp, double nu)
 {
-    static double gx[8], gw[8];
-    static bool init = false;
-    if (!init) { gauss_legendre_pos(8, gx, gw); init = true; }
+    struct Rule {
+        double x[8], w[8];
+        Rule() { gauss_legendre_pos(8, x, w); }
+    };
+    static const Rule rule;   // built once, thread-safe (C++11 function-local static)
+    const double* gx = rule.x;
+    const double* gw = rule.w;
     const int panels = 32;
     const double h = kp.hw / panels;
     double tot = 0.0;
@@ -236,9 +240,13 @@ static double host_psihat_deconv(const KernParams& kp, double nu)
         double a = kp.kb_b * kp.kb_b - (2.0 * kPi * nu) * (2.0 * kPi * nu);
         return kPi * kp.kb_inv_norm * host_i0(kp.kb_m * sqrt(std::max(a, 0.0)));
     }
-    static double gx[kGLNodes], gw[kGLNodes];
-    static bool init = false;
-    if (!init) { gauss_legendre_pos(kGLNodes, gx, gw); init = true; }
+    struct Rule {
+        double x[kGLNodes], w[kGLNodes];
+        Rule() { gauss_legendre_pos(kGLNodes, x, w); }
+    };
+    static const Rule rule;   // built once, thread-safe
+    const double* gx = rule.x;
+    const double* gw = rule.w;
     double acc = 0.0;
     for (int q = 0; q < kGLNodes; ++q)
         acc += gw[q] * exp(kp.es_beta * (sqrt(1.0 - gx[q] * gx[q]) - 1.0)) * cos(2.0 * kPi * nu * kp.hw * gx[q]);
@@ -493,7 +501,6 @@ mm_status make_plan(int32_t N, mm_kernel kernel, double tol, mm_prec prec, const
     if (tune && tune->tile > 0) tile = tune->tile <= 1024 ? 1024 : (tune->tile <= 2048 ? 2048 : 4096);
     p->tile = tile;
     p->fused = 0;
-    p->fused_threads = 256;
     return MM_OK;
 }
 

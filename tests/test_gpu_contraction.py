@@ -43,3 +43,34 @@ def test_mfma_contraction_matches_oracle(mm, D, N, Ns, basis, b):
         assert relfro(S[q, 0], So[q, 0]) <= 1e-5, (D, N, Ns[q], relfro(S[q, 0], So[q, 0]))
         assert relfro(R[q, 0], Ro[q, 0]) <= 1e-5, (D, N, Ns[q], relfro(R[q, 0], Ro[q, 0]))
         assert np.array_equal(S[q, 0], S[q, 0].T)
+
+
+def test_beyond_32bit_flat_index(mm):
+    """D = 46341 (D^2 > 2^31) on the MFMA path with a short k range: the correlation
+    step and the split-K reduce index the D x D matrix in 64 bits.  Checked on the
+    last row and column (flat indices past 2^31) against an FP64 contraction of the
+    same coefficients on the host, and diag(R) = 1."""
+    D, N = 46341, 8
+    rng = np.random.default_rng(46341)
+    c = ((rng.normal(size=(D, N + 1)) + 1j * rng.normal(size=(D, N + 1))) * 0.1).astype(np.complex64)
+    c[:, 0] = c[:, 0].real
+    S, R = mm.cov(torch.from_numpy(c).cuda(), 1, D, [N], "fejer")
+    torch.cuda.synchronize()
+    rows = [0, 1, 23170, D - 2, D - 1]
+    Sg = S[0, 0][rows].double().cpu().numpy()            # 5 x D
+    Rg = R[0, 0][rows].double().cpu().numpy()
+    Sc = S[0, 0][:, D - 1].double().cpu().numpy()        # last column
+    diagR = torch.diagonal(R[0, 0]).double().cpu().numpy()
+    del S, R
+    torch.cuda.empty_cache()
+    cd = c.astype(np.complex128)
+    k = np.arange(N + 1)
+    wk = (1.0 - k / N) / (N + 1) * np.where(k == 0, 1.0, 2.0) * (2 * np.pi) ** 2   # Fejer, both signs of k
+    ref = (cd[rows] * wk) @ cd.conj().T                    # 5 x D, complex; Sigma is its real part
+    ref = ref.real
+    var = np.einsum("ik,ik,k->i", cd, cd.conj(), wk).real
+    assert relfro(Sg, ref) <= 1e-5
+    assert relfro(Sc, ref[-1]) <= 1e-5
+    Rref = ref / np.sqrt(var[rows][:, None] * var[None, :])
+    assert relfro(Rg, Rref) <= 1e-5
+    np.testing.assert_allclose(diagR, 1.0, rtol=0, atol=1e-6)

@@ -47,32 +47,42 @@ def universe(mm):
 
 
 def test_universe_sampled_coefficients(universe):
+    """Coefficients of the smallest, a median and the densest series (1e4 to
+    1e6 events, up to about 6.4 events per grid cell) against the oracle at every
+    24th k over 0..N: their relative l2 error (Eq. Der:18 over those k) must be
+    within the requested tol = 1e-6."""
     w, N, coef, _, _ = universe
     counts = (w.offsets[1:] - w.offsets[:-1]).cpu()
     order = torch.argsort(counts).tolist()
     picks = [order[0], order[len(order) // 2], order[-1]]
-    rng = np.random.default_rng(0)
-    ks = np.unique(np.concatenate([[0, 1, N - 1, N], rng.integers(0, N + 1, 60)]))
+    ks = np.arange(0, N + 1, 24, dtype=np.int64)
     for s in picks:
         tt, dd = w.series(s)
-        tt, dd = tt.cpu(), dd.cpu()
-        ref = np.array([oracle.coeffs(tt, dd, w.t0, w.T, int(k), int(k))[0] for k in ks])
+        ref = oracle.coeffs_at(tt.cpu(), dd.cpu(), w.t0, w.T, ks)
         got = coef[s, torch.as_tensor(ks, device=coef.device)].cpu().numpy().astype(np.complex128)
-        scale = np.sqrt(np.mean(np.abs(ref) ** 2))
-        err = np.abs(got - ref) / scale
-        assert np.sqrt(np.mean(err ** 2)) <= MIXED_BAR, (s, int(counts[s]), err.max())
-        assert err.max() <= 10 * MIXED_BAR, (s, int(counts[s]), err.max())
+        err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        assert err <= 1e-6, (s, int(counts[s]), err)
 
 
 def test_universe_sigma_block_vs_oracle(universe):
-    """The Sigma/R entries of the three smallest series (~1e4 events each) against
-    the oracle over all k = 0..N."""
+    """The Sigma/R block of series stratified over the count range -- the
+    smallest series and one at each count decile up to about 1e5 events -- against
+    the oracle over all k = 0..N (an entry depends only on its pair's series, so
+    the block check is exact)."""
     w, N, _, cov, corr = universe
     counts = (w.offsets[1:] - w.offsets[:-1]).cpu()
-    idx = torch.argsort(counts)[:3].tolist()
+    order = torch.argsort(counts).tolist()
+    idx = [order[0]]
+    for q in range(1, 10):
+        s = order[(q * len(order)) // 10]
+        if counts[s] > 1.2e5:
+            break
+        idx.append(s)
+    assert len(idx) >= 5
+    idx = sorted(set(idx))
     sub = w.subset(idx).to("cpu")
     c = oracle.coeffs_batch(sub.offsets, sub.t, sub.dp, sub.t0, sub.T, N)
-    So, Ro = oracle.cov(c, 1, 3, [N], oracle.FEJER)
+    So, Ro = oracle.cov(c, 1, len(idx), [N], oracle.FEJER)
     blk = np.ix_(idx, idx)
     assert relfro(cov[blk], So[0, 0]) <= MIXED_BAR
     assert relfro(corr[blk], Ro[0, 0]) <= MIXED_BAR
