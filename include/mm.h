@@ -191,6 +191,28 @@ mm_status mm_estimate(int32_t G, int32_t D, const int64_t* offsets, const double
                       mm_kernel kernel, double tol, mm_prec prec, const mm_tuning* tune, void* coef, int64_t ldc,
                       void* cov, void* corr, void* ws, size_t ws_bytes, int32_t use_graph, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): mm_estimate with the
+ * same arguments but no workspace argument and no graph recording (launched
+ * directly, as use_graph = 0).  Its workspace is a fixed device array of
+ * MM_SCRATCH_BYTES that the library holds on each GPU it runs on until the process
+ * ends; the caller still passes the inputs and outputs (coef may be NULL, as
+ * there).  The call allocates no device memory and records no graph.
+ *   Sizes: the request's mm_estimate_workspace_size must not exceed
+ *   MM_SCRATCH_BYTES (64 MiB: e.g. 100 series at N = 5000 need 19 MiB, 300 series
+ *   at N = 3000 need 38 MiB), else MM_ERR_WORKSPACE before anything is launched.
+ *   Sharing: every call on one GPU uses that GPU's one array, so calls that
+ *   overlap in time on one GPU (different streams or host threads) race; order
+ *   them.  The array keeps the last call's contents; nothing in it is read before
+ *   the same call writes it.
+ * Results equal mm_estimate's (same kernels) bit for bit.  Errors: as mm_estimate,
+ * plus MM_ERR_WORKSPACE for a request beyond the fixed size. */
+#define MM_SCRATCH_BYTES ((size_t)64 << 20)
+mm_status mm_estimate_noalloc(int32_t G, int32_t D, const int64_t* offsets, const double* t, const void* dp,
+                              int32_t dp_is_fp64, double t0, double T, const int32_t* Ns, int32_t nN,
+                              mm_basis basis, mm_kernel kernel, double tol, mm_prec prec, const mm_tuning* tune,
+                              void* coef, int64_t ldc, void* cov, void* corr, void* stream);
+
 /* Synchronises the device and frees every graph mm_estimate recorded. */
 mm_status mm_graph_cache_clear(void);
 

@@ -39,12 +39,11 @@ hipEvent_t take_event()
 }
 }  // namespace
 
-// Set while this thread records a graph: event records are left out of captures.
-thread_local bool g_capturing = false;
+thread_local bool g_prof_suspended = false;
 
 void prof_begin(const char* name, hipStream_t st)
 {
-    if (!g_prof_on || g_capturing) return;
+    if (!g_prof_on || g_prof_suspended) return;
     std::lock_guard<std::mutex> lk(g_prof_mu);
     hipEvent_t e = take_event();
     if (!e) return;
@@ -54,7 +53,7 @@ void prof_begin(const char* name, hipStream_t st)
 
 void prof_end(const char* name, hipStream_t st)
 {
-    if (!g_prof_on || g_capturing) return;
+    if (!g_prof_on || g_prof_suspended) return;
     std::lock_guard<std::mutex> lk(g_prof_mu);
     auto it = g_prof_open.find(name);
     if (it == g_prof_open.end()) return;
@@ -367,9 +366,11 @@ mm_status mm_estimate(int32_t G, int32_t D, const int64_t* offsets, const double
     if (it == g_graphs.end()) {
         hipGraph_t graph = nullptr;
         if (hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed) != hipSuccess) return MM_ERR_HIP;
-        g_capturing = true;
-        hipError_t e = enqueue();
-        g_capturing = false;
+        hipError_t e;
+        {
+            ProfSuspend quiet;   // event records are left out of captures
+            e = enqueue();
+        }
         hipError_t ec = hipStreamEndCapture(st, &graph);
         if (e != hipSuccess || ec != hipSuccess) {
             if (graph) (void)hipGraphDestroy(graph);

@@ -188,5 +188,13 @@ hipError_t launch_cov_fp64(int32_t G, int32_t D, const void* coef, int64_t ldc, 
 // Optional per-kernel timing with HIP events on the launch stream.
 void prof_begin(const char* name, hipStream_t st);
 void prof_end(const char* name, hipStream_t st);
+// Set on a thread while its launches must not be timed (a graph capture, or the
+// allocation-free entry point, whose events would be created on demand).
+extern thread_local bool g_prof_suspended;
+struct ProfSuspend {
+    bool prev;
+    ProfSuspend() : prev(g_prof_suspended) { g_prof_suspended = true; }
+    ~ProfSuspend() { g_prof_suspended = prev; }
+};
 
 }  // namespace mm

@@ -27,7 +27,7 @@ _BASES = {"dirichlet": DIRICHLET, "fejer": FEJER}
 _PRECS = {"fp64": PLAIN_FP64, "plain": PLAIN_FP64, "mixed": MIXED}
 
 EXPORTED = ["mm_plan_query", "mm_nufft1_workspace_size", "mm_nufft1", "mm_cov_workspace_size", "mm_cov",
-            "mm_estimate_workspace_size", "mm_estimate", "mm_graph_cache_clear",
+            "mm_estimate_workspace_size", "mm_estimate", "mm_estimate_noalloc", "mm_graph_cache_clear",
             "mm_matrix_to_csr_workspace_size", "mm_matrix_to_csr", "mm_snap_times",
             "mm_cov_pairwise_workspace_size", "mm_cov_pairwise",
             "mm_status_string", "mm_profile_enable", "mm_profile_read", "mm_profile_reset"]
@@ -75,6 +75,8 @@ def lib():
         L.mm_estimate_workspace_size.argtypes = [i32, i32, P, i32, i32, f64, i32, P, ctypes.POINTER(sz)]
         L.mm_estimate.argtypes = [i32, i32, P, P, P, i32, f64, f64, P, i32, i32, i32, f64, i32, P, P, i64, P, P, P,
                                   sz, i32, P]
+        L.mm_estimate_noalloc.argtypes = [i32, i32, P, P, P, i32, f64, f64, P, i32, i32, i32, f64, i32, P, P, i64,
+                                          P, P, P]
         L.mm_graph_cache_clear.argtypes = []
         L.mm_snap_times.argtypes = [i64, P, f64, f64, i64, P, P]
         L.mm_cov_pairwise_workspace_size.argtypes = [i32, i32, P, i32, ctypes.POINTER(sz)]
@@ -278,6 +280,42 @@ def estimate(offsets: torch.Tensor, t: torch.Tensor, dp: torch.Tensor, t0: float
         st = lib().mm_estimate(*args, ctypes.c_void_p(cur.cuda_stream))
     _check(st, "mm_estimate")
     return covt, corrt, ws
+
+
+SCRATCH_BYTES = 64 << 20   # MM_SCRATCH_BYTES
+
+
+def estimate_noalloc(offsets: torch.Tensor, t: torch.Tensor, dp: torch.Tensor, t0: float, T: float, G: int, D: int,
+                     Ns, basis="dirichlet", kernel="es", tol: float = 1e-12, prec="fp64", tune=None,
+                     coef: torch.Tensor = None, out=None):
+    """mm_estimate_noalloc: both stages with the library's fixed device scratch
+    (MM_SCRATCH_BYTES per GPU) instead of a workspace argument.  ``out`` =
+    (cov, corr) are written when given (no allocation at all here then), else
+    allocated.  Returns (cov, corr)."""
+    p = _enum(prec, _PRECS, "precision")
+    if not (offsets.is_cuda and t.is_cuda and dp.is_cuda):
+        raise ValueError("offsets, t and dp must be device tensors")
+    if offsets.dtype != torch.int64 or t.dtype != torch.float64 or dp.dtype not in (torch.float32, torch.float64):
+        raise TypeError("offsets int64, t float64, dp float32/float64 expected")
+    if not (offsets.is_contiguous() and t.is_contiguous() and dp.is_contiguous()):
+        raise ValueError("offsets, t and dp must be contiguous")
+    Ns = [int(n) for n in Ns]
+    arr = (ctypes.c_int32 * len(Ns))(*Ns)
+    rdt = torch.float32 if p == MIXED else torch.float64
+    if out is None:
+        covt = torch.empty((len(Ns), G, D, D), dtype=rdt, device=t.device)
+        corrt = torch.empty_like(covt)
+    else:
+        covt, corrt = out
+    tt = _tuning(tune)
+    ldc = coef.stride(0) if coef is not None else 0
+    st = lib().mm_estimate_noalloc(int(G), int(D), _ptr(offsets), _ptr(t), _ptr(dp), int(dp.dtype == torch.float64),
+                                   float(t0), float(T), arr, len(Ns), _enum(basis, _BASES, "basis"),
+                                   _enum(kernel, _KERNELS, "kernel"), float(tol), p,
+                                   ctypes.byref(tt) if tt is not None else None, _ptr(coef), ldc, _ptr(covt),
+                                   _ptr(corrt), _stream())
+    _check(st, "mm_estimate_noalloc")
+    return covt, corrt
 
 
 def graph_cache_clear():
