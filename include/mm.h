@@ -70,8 +70,10 @@ typedef struct {
                                   -1: the paper's rule for both */
     double sigma;              /* oversampling factor of the grid, >= 1.25 */
     int32_t tile;              /* cells per spreading tile (tiled path) */
-    int32_t fused;             /* reserved for an LDS-resident single-workgroup NUFFT of small grids, which
-                                  is not built: every value runs the tiled path */
+    int32_t fused;             /* the fused small-grid NUFFT (MM_MIXED, per-tap polynomials of 4-12 taps, grids of
+                                  at most 8192 cells): one workgroup per series spreads into LDS, runs both FFT
+                                  passes there and writes only c_k.  0 (auto): taken for calls of at least 64
+                                  series; 1: for any call it can run; -1: never (the tiled kernels) */
     double es_beta_per_tap;    /* ES shape: beta = es_beta_per_tap * width (paper: 2.3) */
     int32_t fft_generic;       /* 1: run the grid FFT with the generic in-LDS radix passes even where both
                                   sub-lengths split into register codelets (0: auto) */
@@ -88,7 +90,7 @@ typedef struct {
     int32_t msp;               /* spreading half-width M_sp of the paper's rule (Sec. 2.2.5) */
     int32_t Mr;                /* oversampled grid length (even, 2,3,5-smooth, >= sigma (2N+1)) */
     int32_t L1, L2;            /* Mr/2 = L1 * L2 (two-pass complex FFT) */
-    int32_t fused;             /* always 0 (the LDS-resident single-workgroup path is not built) */
+    int32_t fused;             /* 1 if the fused small-grid NUFFT can run this plan (mm_tuning.fused) */
     int32_t tile;              /* spreading tile of the tiled path */
     double sigma;              /* oversampling factor used in the kernel shape rules */
     double beta;               /* ES beta, Gaussian lambda or Kaiser-Bessel b */

@@ -93,8 +93,9 @@ static hipError_t enqueue_nufft(const Plan& p, const NufftWs& w, char* wsb, int3
     hipError_t e = launch_prep(p, w, wsb, st);
     if (e != hipSuccess) return e;
     if (p.prec == MM_MIXED) {
-        if (p.fused) return so ? hipErrorInvalidValue
-                               : launch_nufft_fused(p, w, wsb, S, offsets, t, dp, dp_is_fp64, t0, T, coef, ldc, st);
+        if (use_fused(p, S))
+            return so ? hipErrorInvalidValue
+                      : launch_nufft_fused(p, w, wsb, S, offsets, t, dp, dp_is_fp64, t0, T, coef, ldc, st);
         return launch_nufft_tiled(p, w, wsb, 0, S, offsets, t, dp, dp_is_fp64, t0, T, coef, ldc, st, so);
     }
     if (so) return hipErrorInvalidValue;
@@ -331,7 +332,7 @@ mm_status mm_estimate(int32_t G, int32_t D, const int64_t* offsets, const double
     // With no coefficient output, one group and one cutoff on the MFMA path, the
     // FFT's row pass writes the contraction's BF16 operands directly (the same
     // values, rounded the same way, as the split step would).
-    const bool fuse = !coef_out && G == 1 && nN == 1 && prec == MM_MIXED && !p.fused && p.fft_ab &&
+    const bool fuse = !coef_out && G == 1 && nN == 1 && prec == MM_MIXED && !use_fused(p, S) && p.fft_ab &&
                       !small_d_limit(D);
     const SplitOut so = fuse ? cov_mfma_split_out(D, Ns[0], wsb + L.cov) : SplitOut{nullptr, nullptr, 0, nullptr};
     auto enqueue = [&]() -> hipError_t {

@@ -16,6 +16,9 @@ constexpr int kMaxSub = 2048;      // longest in-LDS sub-FFT
 constexpr int kMaxTaps = 40;       // spreading taps per event
 constexpr int kMaxCutoffs = 128;   // cutoffs per mm_cov call
 constexpr int kGLNodes = 64;       // positive nodes of the 128-point Gauss-Legendre rule
+constexpr int kFusedMaxCells = 8192;          // largest grid of the fused single-workgroup NUFFT
+constexpr size_t kFusedMaxLds = 80 * 1024;    // its LDS budget (two workgroups per CU)
+constexpr int kFusedMinSeries = 64;           // series from which the planner's "auto" takes it
 
 // Exact unsigned division a / d for a < 2^22, d < 2^20: (a * M) >> 42, M = ceil(2^42/d).
 struct FastDiv {
@@ -100,8 +103,12 @@ struct Plan {
     double poly_err;     // largest deviation of the polynomials from the kernel (FP64 evaluation)
     PolyParams pp;
     int tile;            // cells per spreading tile: 1024, 2048 or 4096 (256 threads x 4, 8, 16 cells)
-    int fused;           // 1: single-workgroup LDS-resident NUFFT per series
+    int fused;           // 1: the fused single-workgroup NUFFT can run this plan (mm_fused.hip)
+    int fused_min_series;   // ... and runs it for calls with at least this many series
 };
+
+// Whether a call on S series takes the fused single-workgroup NUFFT.
+inline bool use_fused(const Plan& p, int32_t S) { return p.fused && S >= p.fused_min_series; }
 
 // Plan construction (host only, no device calls).  Returns MM_OK or an error.
 mm_status make_plan(int32_t N, mm_kernel kernel, double tol, mm_prec prec, const mm_tuning* tune, Plan* p);
@@ -139,9 +146,17 @@ hipError_t launch_nufft_tiled(const Plan& p, const NufftWs& w, char* ws, int32_t
 hipError_t launch_spread_poly(const Plan& p, int s_count, const double* t, const void* dp, int dp_fp64, double t0,
                               double t_end, const int64_t* ranges, int tiles, float* grid, int64_t grid_stride,
                               hipStream_t st);
+// Fused small-grid NUFFT (mm_fused.hip): the tile search over one whole-grid tile,
+// then one workgroup per series from events to coefficients.
 hipError_t launch_nufft_fused(const Plan& p, const NufftWs& w, char* ws, int32_t S, const int64_t* offsets,
                               const double* t, const void* dp, int dp_fp64, double t0, double T,
                               void* coef, int64_t ldc, hipStream_t st);
+bool fused_fits(const Plan& p);
+size_t fused_lds_bytes(const Plan& p);
+// Event ranges of every (series, tile of tc cells) (k_tile_ranges).
+hipError_t launch_tile_ranges(const Plan& p, const int64_t* offsets, const double* t, int32_t s_begin,
+                              int32_t s_count, int tiles, int tc, double t0, double T, int64_t* ranges,
+                              hipStream_t st);
 
 // Two-pass grid FFT with one LDS exchange per pass (mm_fft.hip).
 bool fft_ab_split(int n, int max_codelet, int* A, int* B);

@@ -500,7 +500,11 @@ mm_status make_plan(int32_t N, mm_kernel kernel, double tol, mm_prec prec, const
     int tile = (prec == MM_MIXED) ? 2048 : 1024;
     if (tune && tune->tile > 0) tile = tune->tile <= 1024 ? 1024 : (tune->tile <= 2048 ? 2048 : 4096);
     p->tile = tile;
-    p->fused = 0;
+    // the fused single-workgroup NUFFT of small grids: 0 (auto) for calls of at least
+    // kFusedMinSeries series, 1 for any call, -1 never
+    const int fz = tune ? tune->fused : 0;
+    p->fused = (fz >= 0 && fused_fits(*p)) ? 1 : 0;
+    p->fused_min_series = fz == 1 ? 1 : kFusedMinSeries;
     return MM_OK;
 }
 
@@ -523,9 +527,10 @@ NufftWs nufft_workspace(const Plan& p, int32_t S)
     w.tMlo = o; o += al(2 * rs * ((size_t)1 << p.tw_lo_bits));
     w.tMhi = o; o += al(2 * rs * (size_t)p.tw_hi_M);
     w.flag = o; o += 256;
-    w.S_grid = (p.prec == MM_MIXED && !p.fused) ? S : (p.fused ? 0 : 1);
+    const bool fused = use_fused(p, S);
+    w.S_grid = fused ? 0 : (p.prec == MM_MIXED ? S : 1);
     const size_t tiles = (size_t)(p.Mr + p.tile - 1) / p.tile;
-    w.ranges = o; o += al(8 * 6 * tiles * (size_t)w.S_grid);
+    w.ranges = o; o += al(8 * 6 * (fused ? (size_t)S : tiles * (size_t)w.S_grid));
     w.grid = o; o += al(rs * 2 * (size_t)p.L1 * (size_t)p.L2p * (size_t)w.S_grid);
     w.total = o;
     return w;
