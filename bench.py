@@ -57,7 +57,7 @@ def parse():
     ap.add_argument("--sigma", type=float, default=0.0, help="override the oversampling factor")
     ap.add_argument("--untuned", action="store_true",
                     help="the planner's defaults (sigma = 2) instead of the autotuned large-universe plan")
-    ap.add_argument("--workload", default="large-universe", choices=("large-universe", "replicates", "cross-section"),
+    ap.add_argument("--workload", default="large-universe", choices=("large-universe", "replicates", "cross-section", "pairwise"),
                     help="large-universe (the default bench line), or the Monte Carlo replicates / 100-asset "
                          "cross-section timed through mm_estimate")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -315,6 +315,42 @@ def estimate_bench(a, workload):
     return res
 
 
+def pairwise_bench(a):
+    """Per-pair cutoffs N_ij = min(N_i, N_j) on the large universe: every asset with
+    its own cutoff (log-spaced over [1000, N], shuffled), mm_cov_pairwise on the
+    mixed coefficients (best of 3) beside mm_cov at the single cutoff N and the FP64
+    form of the per-pair product; Sigma/R error against that FP64 form."""
+    import numpy as np
+    import torch
+
+    from paper_2003_02842_amd import mm, synth
+    from paper_2003_02842_amd.tune import LARGE_UNIVERSE
+
+    w = synth.large_universe(D=a.D, n_lo=a.n_lo, n_hi=a.n_hi, N=a.N, seed=a.seed, device="cuda")
+    D, N = w.S, a.N
+    rng = np.random.default_rng(a.seed)
+    levels = np.unique(np.round(np.geomspace(1000, N, 4 * D)).astype(int))
+    Ni = [int(v) for v in rng.permutation(levels[np.linspace(0, levels.size - 1, D).astype(int)])]
+    c = mm.nufft1(w.offsets, w.t, w.dp, w.t0, w.T, N, a.kernel, a.tol, "mixed", dict(LARGE_UNIVERSE))
+    ws = torch.empty(max(mm.cov_workspace_size(1, D, N, 1, "mixed"), 256), dtype=torch.uint8, device="cuda")
+    pair_ms = _best_of(lambda: mm.cov_pairwise(c, 1, D, Ni, a.basis), 3)
+    single_ms = _best_of(lambda: mm.cov(c, 1, D, [N], a.basis, ws=ws), 3)
+    S, R = mm.cov_pairwise(c, 1, D, Ni, a.basis)
+    del c, ws
+    torch.cuda.empty_cache()
+    c64 = mm.nufft1(w.offsets, w.t, w.dp.double(), w.t0, w.T, N, a.kernel, 1e-12, "fp64")
+    t = time.perf_counter()
+    S64, R64 = mm.cov_pairwise(c64, 1, D, Ni, a.basis)
+    torch.cuda.synchronize()
+    fp64_ms = 1e3 * (time.perf_counter() - t)
+    errs = {"cov": _relfro_max(S[None], S64[None]), "corr": _relfro_max(R[None], R64[None])}
+    del c64, S, R, S64, R64
+    torch.cuda.empty_cache()
+    return {"ms": pair_ms, "distinct_cutoffs": len(set(Ni)), "cutoff_range": [min(Ni), max(Ni)],
+            "single_cutoff_mm_cov_ms": single_ms, "plain_fp64_pairwise_ms": fp64_ms, "rel_err_vs_fp64": errs,
+            "config": "large universe, %d assets each with its own cutoff, %s basis, mixed" % (D, a.basis)}
+
+
 def main():
     a = parse()
     if a.copy_calibration:
@@ -322,6 +358,9 @@ def main():
     if a.gpus != 1:
         print("bench.py: this build runs on exactly one GPU; --gpus %d is not supported" % a.gpus, file=sys.stderr)
         return 2
+    if a.workload == "pairwise":
+        print(json.dumps(pairwise_bench(a)), flush=True)
+        return 0
     if a.workload != "large-universe":
         print(json.dumps(estimate_bench(a, a.workload)), flush=True)
         return 0
@@ -531,6 +570,7 @@ def main():
                 "value", "unit", "ms_per_step", "launch", "graph_ms_per_step", "eager_ms_per_step", "kernels_ms",
                 "mixed_rerun_per_cutoff_ms", "plain_fp64_reuse_ms", "speedup_vs_plain_fp64",
                 "speedup_vs_rerun_per_cutoff", "rel_err_vs_fp64", "config", "dtype")}
+        out["pairwise"] = pairwise_bench(ea)
     print(json.dumps(out), flush=True)
     return 0
 

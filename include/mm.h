@@ -228,14 +228,19 @@ mm_status mm_cov_pairwise_workspace_size(int32_t G, int32_t D, const int32_t* Ni
  *   corr[g][i][j] = cov_ij(N_ij) / sqrt(cov_ii(N_ij) cov_jj(N_ij)), the correlation of the
  *                  pairwise 2 x 2 estimate (NaN for a non-positive variance); may be NULL
  * The diagonal holds each asset's variance at its own N_i.  One coefficient set
- * (columns 0..max N_i) serves all pairs: the estimate is swept over the distinct
- * cutoffs (at most 128) and each entry read from its pair's cutoff.
+ * (columns 0..max N_i) serves all pairs, with any number of distinct cutoffs: for
+ * small D (D(D+1)/2 <= 1024) the estimate is swept over the distinct cutoffs and
+ * each entry read from its pair's cutoff; otherwise the assets are taken in
+ * ascending order of cutoff, so that a pair's cutoff is the lower-ranked asset's,
+ * and one product of unweighted coefficients with coefficients weighted at each
+ * asset's own cutoff gives every entry (BF16 hi/lo MFMA on MM_MIXED, FP64 tiles on
+ * MM_PLAIN_FP64); the correlations take each asset's variance at every cutoff up
+ * to its own from a prefix-sum table.
  *   coef   (G*D) x ldc as for mm_cov, ldc >= max N_i + 1
  *   Ni     host int32[D], each >= 1, shared by all groups
  *   cov, corr  G x D x D, float (MM_MIXED) or double (MM_PLAIN_FP64)
  * Synchronises `stream`.  The result need not be positive semi-definite.
- * Errors: MM_ERR_ARG, MM_ERR_WORKSPACE, MM_ERR_UNSUPPORTED (more than 128 distinct cutoffs),
- * MM_ERR_HIP. */
+ * Errors: MM_ERR_ARG, MM_ERR_WORKSPACE, MM_ERR_UNSUPPORTED (G or D above 65535), MM_ERR_HIP. */
 mm_status mm_cov_pairwise(int32_t G, int32_t D, const void* coef, int64_t ldc, const int32_t* Ni, mm_basis basis,
                           mm_prec prec, void* cov, void* corr, void* ws, size_t ws_bytes, void* stream);
 

@@ -451,19 +451,30 @@ static bool pairwise_cutoffs(int32_t D, const int32_t* Ni, std::vector<int32_t>&
     Ns.assign(Ni, Ni + D);
     std::sort(Ns.begin(), Ns.end());
     Ns.erase(std::unique(Ns.begin(), Ns.end()), Ns.end());
-    if (Ns.empty() || Ns.front() < 1 || (int)Ns.size() > kMaxCutoffs) return false;
+    if (Ns.empty() || Ns.front() < 1) return false;
     slot.resize(D);
     for (int i = 0; i < D; ++i) slot[i] = (int32_t)(std::lower_bound(Ns.begin(), Ns.end(), Ni[i]) - Ns.begin());
     return true;
 }
 
+// Small D: the estimate swept over the distinct cutoffs (D <= 45, so at most 45 of
+// them) and each entry read from its pair's slice.  Otherwise one product over the
+// rows in ascending-cutoff order, whatever the number of distinct cutoffs.
+static bool pairwise_sweep(int32_t D) { return small_d_limit(D); }
+
 static size_t pairwise_layout(int32_t G, int32_t D, int32_t Nmax, int32_t nq, mm_prec prec, size_t* sweep_off,
                               size_t* cov_off)
 {
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    if (!pairwise_sweep(D)) {
+        // tables: perm, Nr, rank, slot (D each) and cutq (Nmax + 1), then the product's workspace
+        *sweep_off = 0;
+        *cov_off = al(4 * (4 * (size_t)D + (size_t)Nmax + 1));
+        return *cov_off + cov_pair_workspace(prec, G, D, Nmax, nq);
+    }
     const size_t es = prec == MM_MIXED ? 4 : 8;
     size_t cw = 0;
     mm_cov_workspace_size(G, D, Nmax, nq, prec, &cw);
-    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
     *sweep_off = al(4 * (size_t)D);
     *cov_off = *sweep_off + al((size_t)nq * G * D * D * es);
     return *cov_off + al(cw);
@@ -473,7 +484,7 @@ mm_status mm_cov_pairwise_workspace_size(int32_t G, int32_t D, const int32_t* Ni
 {
     if (!bytes || !Ni || G < 1 || D < 1 || (prec != MM_PLAIN_FP64 && prec != MM_MIXED)) return MM_ERR_ARG;
     std::vector<int32_t> Ns, slot;
-    if (!pairwise_cutoffs(D, Ni, Ns, slot)) return (Ns.size() > (size_t)kMaxCutoffs) ? MM_ERR_UNSUPPORTED : MM_ERR_ARG;
+    if (!pairwise_cutoffs(D, Ni, Ns, slot)) return MM_ERR_ARG;
     size_t a, b;
     *bytes = pairwise_layout(G, D, Ns.back(), (int32_t)Ns.size(), prec, &a, &b);
     return MM_OK;
@@ -486,21 +497,49 @@ mm_status mm_cov_pairwise(int32_t G, int32_t D, const void* coef, int64_t ldc, c
     if (basis != MM_DIRICHLET && basis != MM_FEJER) return MM_ERR_ARG;
     if (prec != MM_PLAIN_FP64 && prec != MM_MIXED) return MM_ERR_ARG;
     std::vector<int32_t> Ns, slot;
-    if (!pairwise_cutoffs(D, Ni, Ns, slot)) return (Ns.size() > (size_t)kMaxCutoffs) ? MM_ERR_UNSUPPORTED : MM_ERR_ARG;
+    if (!pairwise_cutoffs(D, Ni, Ns, slot)) return MM_ERR_ARG;
     const int32_t nq = (int32_t)Ns.size(), Nmax = Ns.back();
     if ((int64_t)Nmax > ldc - 1) return MM_ERR_ARG;
-    if (small_d_limit(D) && G > 65535) return MM_ERR_UNSUPPORTED;
+    if (pairwise_sweep(D) && G > 65535) return MM_ERR_UNSUPPORTED;
+    if (!pairwise_sweep(D) && (D > 65535 || G > 65535)) return MM_ERR_UNSUPPORTED;
     size_t sweep_off, cov_off;
     const size_t need = pairwise_layout(G, D, Nmax, nq, prec, &sweep_off, &cov_off);
     if (!ws || ws_bytes < need) return MM_ERR_WORKSPACE;
     if (((uintptr_t)ws & 255) != 0) return MM_ERR_ARG;
     hipStream_t st = (hipStream_t)stream;
     char* wsb = (char*)ws;
-    if (hipMemcpyAsync(wsb, slot.data(), 4 * (size_t)D, hipMemcpyHostToDevice, st) != hipSuccess) return MM_ERR_HIP;
-    hipError_t e = enqueue_cov(G, D, coef, ldc, Ns.data(), nq, Nmax, basis, prec, wsb + sweep_off, nullptr,
-                               wsb + cov_off, st);
-    if (e == hipSuccess) e = launch_pairwise_select(prec, G, D, (const int32_t*)wsb, wsb + sweep_off, cov, corr, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);   // the host slot table must outlive the copy
+    hipError_t e;
+    if (pairwise_sweep(D)) {
+        if (hipMemcpyAsync(wsb, slot.data(), 4 * (size_t)D, hipMemcpyHostToDevice, st) != hipSuccess)
+            return MM_ERR_HIP;
+        e = enqueue_cov(G, D, coef, ldc, Ns.data(), nq, Nmax, basis, prec, wsb + sweep_off, nullptr, wsb + cov_off,
+                        st);
+        if (e == hipSuccess)
+            e = launch_pairwise_select(prec, G, D, (const int32_t*)wsb, wsb + sweep_off, cov, corr, st);
+    } else {
+        // rows in ascending order of cutoff (stable), their cutoffs, ranks and slots,
+        // and the slot of every k that is a cutoff
+        std::vector<int32_t> tab(4 * (size_t)D + (size_t)Nmax + 1, -1);
+        int32_t* perm = tab.data();
+        int32_t* Nr = perm + D;
+        int32_t* rank = Nr + D;
+        int32_t* rslot = rank + D;
+        int32_t* cutq = rslot + D;
+        for (int i = 0; i < D; ++i) perm[i] = i;
+        std::stable_sort(perm, perm + D, [&](int32_t a, int32_t b) { return Ni[a] < Ni[b]; });
+        for (int r = 0; r < D; ++r) {
+            Nr[r] = Ni[perm[r]];
+            rank[perm[r]] = r;
+            rslot[r] = slot[perm[r]];
+        }
+        for (int q = 0; q < nq; ++q) cutq[Ns[q]] = q;
+        if (hipMemcpyAsync(wsb, tab.data(), 4 * tab.size(), hipMemcpyHostToDevice, st) != hipSuccess)
+            return MM_ERR_HIP;
+        const int32_t* dt = (const int32_t*)wsb;
+        const PairTables tb{dt, dt + D, dt + 2 * D, dt + 3 * D, dt + 4 * D};
+        e = launch_cov_pair(prec, G, D, coef, ldc, Nmax, tb, nq, basis, cov, corr, wsb + cov_off, st);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);   // the host tables must outlive the copy
     return hip_status(e);
 }
 

@@ -261,6 +261,7 @@ __global__ void k_split_bf16(int D, const float2* __restrict__ coef, int64_t ldc
 // the XCD-aware order of syrk_work_item, so that the tiles sharing a row panel
 // read it through one XCD's L2.
 __global__ __launch_bounds__(256) void k_syrk_mfma(const uint16_t* __restrict__ hi, const uint16_t* __restrict__ lo,
+                                                   const uint16_t* __restrict__ bhi, const uint16_t* __restrict__ blo,
                                                    int64_t Kp, int64_t kchunk, int ntiles, int nsplit,
                                                    float* __restrict__ partial)
 {
@@ -280,8 +281,8 @@ __global__ __launch_bounds__(256) void k_syrk_mfma(const uint16_t* __restrict__ 
     const int wy = wave >> 1, wx = wave & 1;
     const uint16_t* Ah = hi + (int64_t)bi * ST * Kp;
     const uint16_t* Al = lo + (int64_t)bi * ST * Kp;
-    const uint16_t* Bh = hi + (int64_t)bj * ST * Kp;
-    const uint16_t* Bl = lo + (int64_t)bj * ST * Kp;
+    const uint16_t* Bh = bhi + (int64_t)bj * ST * Kp;
+    const uint16_t* Bl = blo + (int64_t)bj * ST * Kp;
     f32x16 acc[2][2];
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b)
@@ -431,7 +432,9 @@ __device__ __forceinline__ void syrk256_stage_dma(const uint4* __restrict__ L, u
 }
 
 __global__ __launch_bounds__(256) void k_syrk_mfma256(const uint16_t* __restrict__ hi,
-                                                      const uint16_t* __restrict__ lo, int64_t Kp, int64_t kchunk,
+                                                      const uint16_t* __restrict__ lo,
+                                                      const uint16_t* __restrict__ bhi,
+                                                      const uint16_t* __restrict__ blo, int64_t Kp, int64_t kchunk,
                                                       int ntiles, int nsplit, float* __restrict__ partial)
 {
     __shared__ uint4 lds0[4 * T2 * 4];   // [array: A hi, A lo, B hi, B lo][row][chunk], even stages
@@ -442,7 +445,9 @@ __global__ __launch_bounds__(256) void k_syrk_mfma256(const uint16_t* __restrict
     while (bi * (bi + 1) / 2 > t) --bi;
     while ((bi + 1) * (bi + 2) / 2 <= t) ++bi;
     const int bj = t - bi * (bi + 1) / 2;
-    const bool diag = bi == bj;
+    // a diagonal tile of X X^T (B the same arrays as A) stages one panel and skips
+    // its upper quadrant; a product A B^T with B of its own computes every quadrant
+    const bool diag = bi == bj && bhi == hi;
     const int64_t kb = (int64_t)split * kchunk;
     const int64_t ke = min(kb + kchunk, Kp);
     const int nst = (int)((ke - kb) / SK2);
@@ -450,7 +455,7 @@ __global__ __launch_bounds__(256) void k_syrk_mfma256(const uint16_t* __restrict
     const int wy = wave >> 1, wx = wave & 1;
     const bool active = !(diag && wy == 0 && wx == 1);
     const char* const src[4] = {(const char*)(hi + (int64_t)bi * T2 * Kp), (const char*)(lo + (int64_t)bi * T2 * Kp),
-                                (const char*)(hi + (int64_t)bj * T2 * Kp), (const char*)(lo + (int64_t)bj * T2 * Kp)};
+                                (const char*)(bhi + (int64_t)bj * T2 * Kp), (const char*)(blo + (int64_t)bj * T2 * Kp)};
     uint32_t goff[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -513,8 +518,12 @@ __global__ __launch_bounds__(256) void k_syrk_mfma256(const uint16_t* __restrict
 // so that four loads of the split are in flight at once.
 template <int TS>
 __global__ __launch_bounds__(256) void k_syrk_reduce(const float* __restrict__ partial, int nsplit, int ntiles, int D,
-                                                     float* __restrict__ cov)
+                                                     float* __restrict__ cov, const int32_t* __restrict__ perm)
 {
+    // row i of the product is series perm[i] (the identity when perm is NULL)
+    auto at = [&](int i, int j) -> int64_t {
+        return perm ? (int64_t)perm[i] * D + perm[j] : (int64_t)i * D + j;
+    };
     constexpr int ST = TS;
     constexpr int QN = TS / 64;   // 64 x 64 sub-blocks per tile edge
     constexpr int RB = 16;        // rows per workgroup
@@ -549,12 +558,12 @@ __global__ __launch_bounds__(256) void k_syrk_reduce(const float* __restrict__ p
             // diagonal tile: (i, j) and (j, i) both come from the lower entry, so that
             // Sigma is exactly symmetric (the MFMA sums the two in different orders)
             if (i < D && j <= i) {
-                cov[(int64_t)i * D + j] = acc;
-                cov[(int64_t)j * D + i] = acc;
+                cov[at(i, j)] = acc;
+                cov[at(j, i)] = acc;
             }
             continue;
         }
-        if (i < D && j < D) cov[(int64_t)i * D + j] = acc;
+        if (i < D && j < D) cov[at(i, j)] = acc;
         tileT[r][tx] = acc;
     }
     if (bi == bj) return;
@@ -563,7 +572,7 @@ __global__ __launch_bounds__(256) void k_syrk_reduce(const float* __restrict__ p
     for (int e = threadIdx.x; e < 64 * RB; e += 256) {
         const int c = e / RB, r = e % RB;
         const int j = bj * ST + qj + c, i = bi * ST + qi + part * RB + r;
-        if (i < D && j < D) cov[(int64_t)j * D + i] = tileT[r][c];
+        if (i < D && j < D) cov[at(j, i)] = tileT[r][c];
     }
 }
 
@@ -602,6 +611,181 @@ hipError_t launch_pairwise_select(int prec, int32_t G, int32_t D, const int32_t*
         hipLaunchKernelGGL(k_pairwise_select<double>, dim3(blocks), dim3(256), 0, st, total, D, G, qidx,
                            (const double*)sweep, (double*)cov, (double*)corr);
     return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ per-pair cutoffs
+// With per-asset cutoffs (Sec. 3), pair (i, j) is estimated at N_ij = min(N_i, N_j).
+// Rows are taken in ascending order of cutoff (row r is series perm[r], cutoff
+// Nr[r]), so that for r >= q the pair's cutoff is the column's, N_q, and
+//   Sigma_rq = (2pi)^2 sum_{k <= N_q} m_k w_k(N_q) Re(c^r_k conj c^q_k) = sum_k A_rk B_qk
+// with A_rk = 2pi sqrt(m_k) c^r_k (k <= N_r) and B_qk = 2pi sqrt(m_k) w_k(N_q) c^q_k
+// (k <= N_q): one product A B^T over the lower triangle, however many distinct
+// cutoffs there are.  The weights: Dirichlet 1/(2N+1), Fejer (1 - k/N)/(N+1).
+
+// A and B of one group as BF16 hi/lo pairs (row = sorted position, column pair k).
+__global__ void k_pair_split(int D, const float2* __restrict__ coef, int64_t ldc, const int32_t* __restrict__ perm,
+                             const int32_t* __restrict__ Nr, int basis, int64_t Kp, uint32_t* __restrict__ ahi,
+                             uint32_t* __restrict__ alo, uint32_t* __restrict__ bhi, uint32_t* __restrict__ blo)
+{
+    const int row = blockIdx.y;                        // < Dp
+    const bool real_row = row < D;
+    const int src = real_row ? perm[row] : 0;
+    const int N = real_row ? Nr[row] : -1;
+    // per-row weight constants in FP64: w_k = w0 (Dirichlet) or (1 - k/N) w0 (Fejer)
+    const double w0 = basis == MM_DIRICHLET ? 1.0 / (2.0 * N + 1.0) : 1.0 / (N + 1.0);
+    const double invN = 1.0 / (double)N;
+    const float two_pi = (float)kTwoPi, two_pi_r2 = (float)(kTwoPi * 1.4142135623730950488);
+    const int64_t kp2 = Kp / 2;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < kp2; c += (int64_t)gridDim.x * blockDim.x) {
+        const int k = (int)c;
+        float2 cc = make_float2(0.f, 0.f);
+        float sa = 0.f, sb = 0.f;
+        if (real_row && k <= N) {
+            cc = coef[(int64_t)src * ldc + k];
+            sa = k ? two_pi_r2 : two_pi;                  // 2pi sqrt(m_k)
+            const double w = basis == MM_DIRICHLET ? w0 : (1.0 - (double)k * invN) * w0;
+            sb = (float)((k ? kTwoPi * 1.4142135623730950488 : kTwoPi) * w);
+        }
+        uint32_t h, l;
+        const int64_t at = (int64_t)row * kp2 + c;
+        bf16_split_pair(cc.x, cc.y, sa, h, l);
+        ahi[at] = h;
+        alo[at] = l;
+        bf16_split_pair(cc.x, cc.y, sb, h, l);
+        bhi[at] = h;
+        blo[at] = l;
+    }
+}
+
+// Variances at every distinct cutoff up to a row's own: one wave per (group, row)
+// scans k = 0..N_r with FP64 running sums S0 = sum m_k |c_k|^2 and
+// S1 = sum m_k k |c_k|^2 (an inclusive scan over each 64 k, plus the carry); the
+// lane at k = N_q (cutq[k] = q) writes var[row][q], Dirichlet (2pi)^2 S0/(2N+1) or
+// Fejer (2pi)^2 (S0 - S1/N)/(N+1).
+template <typename CT, typename OT>
+__global__ __launch_bounds__(64) void k_pair_var(int D, const CT* __restrict__ coef, int64_t ldc,
+                                                 const int32_t* __restrict__ perm, const int32_t* __restrict__ Nr,
+                                                 const int32_t* __restrict__ cutq, int nq, int basis,
+                                                 OT* __restrict__ var)
+{
+    const int row = blockIdx.x, g = blockIdx.y;
+    const int lane = (int)threadIdx.x;
+    const int N = Nr[row];
+    const CT* c = coef + ((int64_t)g * D + perm[row]) * ldc;
+    OT* out = var + ((int64_t)g * D + row) * nq;
+    const double fourpi2 = kTwoPi * kTwoPi;
+    double carry0 = 0.0, carry1 = 0.0;
+    for (int k0 = 0; k0 <= N; k0 += 64) {
+        const int k = k0 + lane;
+        double v0 = 0.0;
+        if (k <= N) {
+            const double2 u = to_d2(c[k]);
+            v0 = (k ? 2.0 : 1.0) * (u.x * u.x + u.y * u.y);
+        }
+        double v1 = (double)k * v0;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const double a0 = __shfl_up(v0, o), a1 = __shfl_up(v1, o);
+            if (lane >= o) {
+                v0 += a0;
+                v1 += a1;
+            }
+        }
+        const double S0 = carry0 + v0, S1 = carry1 + v1;
+        if (k <= N) {
+            const int q = cutq[k];
+            if (q >= 0) {
+                const double Nd = (double)k;
+                const double v = basis == MM_DIRICHLET ? S0 / (2.0 * Nd + 1.0) : (S0 - S1 / Nd) / (Nd + 1.0);
+                out[q] = (OT)(fourpi2 * v);
+            }
+        }
+        carry0 = __shfl(S0, 63);
+        carry1 = __shfl(S1, 63);
+    }
+}
+
+// Correlations of the pairwise estimates: entry (a, b) at N_ab from the variances
+// of both series at that cutoff (the slot of the lower-ranked series' cutoff);
+// on the diagonal Sigma_aa / (sqrt Sigma_aa)^2.  NaN for a non-positive variance.
+template <typename OT>
+__global__ void k_pair_corr(int64_t total, int D, const int32_t* __restrict__ rank, const int32_t* __restrict__ slot,
+                            const OT* __restrict__ var, int nq, const OT* __restrict__ cov, OT* __restrict__ corr)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    const int64_t DD = (int64_t)D * D;
+    const int64_t g = idx / DD;
+    const int64_t r = idx - g * DD;
+    const int a = (int)(r / D), b = (int)(r - (int64_t)a * D);
+    const OT v = cov[idx];
+    OT va, vb;
+    if (a == b) {
+        va = vb = v;
+    } else {
+        const int ra = rank[a], rb = rank[b];
+        const int q = slot[min(ra, rb)];
+        va = var[((int64_t)g * D + ra) * nq + q];
+        vb = var[((int64_t)g * D + rb) * nq + q];
+    }
+    corr[idx] = (va > (OT)0 && vb > (OT)0) ? v / (sqrt(va) * sqrt(vb)) : (OT)NAN;
+}
+
+// The FP64 form of the per-pair product: lower-triangle 64 x 64 tiles over the
+// sorted rows, A unweighted, B = (2pi)^2 m_k w_k(N_q) c^q_k, written to the
+// series' own positions (both halves).
+__global__ __launch_bounds__(256) void k_pair_fp64(int D, const double2* __restrict__ coef, int64_t ldc, int Nmax,
+                                                   const int32_t* __restrict__ perm, const int32_t* __restrict__ Nr,
+                                                   int basis, double* __restrict__ cov)
+{
+    __shared__ double2 sA[F64K][F64T + 1];
+    __shared__ double2 sB[F64K][F64T + 1];
+    const int t = blockIdx.x;
+    int bi = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while (bi * (bi + 1) / 2 > t) --bi;
+    while ((bi + 1) * (bi + 2) / 2 <= t) ++bi;
+    const int bj = t - bi * (bi + 1) / 2;
+    const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+    double acc[4][4];
+    for (int u = 0; u < 4; ++u)
+        for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+    const double fourpi2 = kTwoPi * kTwoPi;
+    for (int k0 = 0; k0 <= Nmax; k0 += F64K) {
+        for (int idx = threadIdx.x; idx < F64T * F64K; idx += 256) {
+            const int r = idx >> 4, kk = idx & 15;
+            const int k = k0 + kk;
+            const int ia = bi * F64T + r, ib = bj * F64T + r;
+            double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
+            if (ia < D && k <= Nr[ia]) a = coef[(int64_t)perm[ia] * ldc + k];
+            if (ib < D && k <= Nr[ib]) {
+                const double N = (double)Nr[ib];
+                const double w = basis == MM_DIRICHLET ? 1.0 / (2.0 * N + 1.0) : (1.0 - (double)k / N) / (N + 1.0);
+                const double wk = (k ? 2.0 : 1.0) * w * fourpi2;
+                const double2 bb = coef[(int64_t)perm[ib] * ldc + k];
+                b = make_double2(bb.x * wk, bb.y * wk);
+            }
+            sA[kk][r] = a;
+            sB[kk][r] = b;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int kk = 0; kk < F64K; ++kk) {
+            double2 a[4], b[4];
+            for (int u = 0; u < 4; ++u) a[u] = sA[kk][ty * 4 + u];
+            for (int v = 0; v < 4; ++v) b[v] = sB[kk][tx * 4 + v];
+            for (int u = 0; u < 4; ++u)
+                for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u].x, b[v].x, fma(a[u].y, b[v].y, acc[u][v]));
+        }
+        __syncthreads();
+    }
+    for (int u = 0; u < 4; ++u)
+        for (int v = 0; v < 4; ++v) {
+            const int i = bi * F64T + ty * 4 + u, j = bj * F64T + tx * 4 + v;
+            if (i < D && j <= i) {   // r >= q: the column's cutoff is the pair's
+                cov[(int64_t)perm[i] * D + perm[j]] = acc[u][v];
+                cov[(int64_t)perm[j] * D + perm[i]] = acc[u][v];
+            }
+        }
 }
 
 // ------------------------------------------------------------------------------- launchers
@@ -805,6 +989,108 @@ hipError_t launch_split_prologue(int32_t D, int32_t N, int basis, char* ws, hipS
     return hipGetLastError();
 }
 
+// Workspace of the one-pass per-pair product (after the caller's tables): the
+// variance table, then (MM_MIXED) the A and B operands and the split-K partials.
+struct PairShape {
+    MfmaShape m;
+    size_t var, bhi, blo, mfma, total;
+};
+
+static PairShape pair_shape(int prec, int32_t G, int32_t D, int32_t Nmax, int32_t nq)
+{
+    PairShape s;
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t es = prec == MM_MIXED ? 4 : 8;
+    s.var = 0;
+    size_t o = al((size_t)G * D * nq * es);
+    if (prec == MM_MIXED) {
+        s.m = mfma_shape(D, Nmax);
+        s.bhi = o; o += al((size_t)s.m.Dp * s.m.Kp * 2);
+        s.blo = o; o += al((size_t)s.m.Dp * s.m.Kp * 2);
+        s.mfma = o; o += s.m.total;
+    } else {
+        s.bhi = s.blo = s.mfma = o;
+    }
+    s.total = o;
+    return s;
+}
+
+size_t cov_pair_workspace(int prec, int32_t G, int32_t D, int32_t Nmax, int32_t nq)
+{
+    return pair_shape(prec, G, D, Nmax, nq).total;
+}
+
+hipError_t launch_cov_pair(int prec, int32_t G, int32_t D, const void* coef, int64_t ldc, int32_t Nmax,
+                           const PairTables& tb, int32_t nq, int basis, void* cov, void* corr, char* ws,
+                           hipStream_t st)
+{
+    const PairShape s = pair_shape(prec, G, D, Nmax, nq);
+    const size_t es = prec == MM_MIXED ? 4 : 8;
+    for (int g = 0; g < G; ++g) {
+        char* cg = (char*)cov + (size_t)g * D * D * es;
+        if (prec == MM_MIXED) {
+            const MfmaShape& m = s.m;
+            char* w = ws + s.mfma;
+            uint16_t* ahi = (uint16_t*)(w + m.hi);
+            uint16_t* alo = (uint16_t*)(w + m.lo);
+            uint16_t* bhi = (uint16_t*)(ws + s.bhi);
+            uint16_t* blo = (uint16_t*)(ws + s.blo);
+            float* part = (float*)(w + m.partial);
+            const int bx = (int)std::min<int64_t>((m.Kp / 2 + 255) / 256, 64);
+            prof_begin("k_pair_split", st);
+            hipLaunchKernelGGL(k_pair_split, dim3(bx, m.Dp), dim3(256), 0, st, D,
+                               (const float2*)coef + (int64_t)g * D * ldc, ldc, tb.perm, tb.Nr, basis, m.Kp,
+                               (uint32_t*)ahi, (uint32_t*)alo, (uint32_t*)bhi, (uint32_t*)blo);
+            prof_end("k_pair_split", st);
+            const char* name = m.ts == T2 ? "k_syrk_mfma256" : "k_syrk_mfma";
+            prof_begin(name, st);
+            if (m.ts == T2)
+                hipLaunchKernelGGL(k_syrk_mfma256, dim3((unsigned)(m.ntiles * m.nsplit)), dim3(256), 0, st, ahi, alo,
+                                   bhi, blo, m.Kp, m.kchunk, m.ntiles, m.nsplit, part);
+            else
+                hipLaunchKernelGGL(k_syrk_mfma, dim3((unsigned)(m.ntiles * m.nsplit)), dim3(256), 0, st, ahi, alo,
+                                   bhi, blo, m.Kp, m.kchunk, m.ntiles, m.nsplit, part);
+            prof_end(name, st);
+            prof_begin("k_syrk_reduce", st);
+            if (m.ts == T2)
+                hipLaunchKernelGGL(k_syrk_reduce<T2>, dim3((unsigned)(64 * m.ntiles)), dim3(256), 0, st, part,
+                                   m.nsplit, m.ntiles, D, (float*)cg, tb.perm);
+            else
+                hipLaunchKernelGGL(k_syrk_reduce<ST>, dim3((unsigned)(16 * m.ntiles)), dim3(256), 0, st, part,
+                                   m.nsplit, m.ntiles, D, (float*)cg, tb.perm);
+            prof_end("k_syrk_reduce", st);
+        } else {
+            const int tn = (D + F64T - 1) / F64T;
+            prof_begin("k_pair_fp64", st);
+            hipLaunchKernelGGL(k_pair_fp64, dim3(tn * (tn + 1) / 2), dim3(256), 0, st, D,
+                               (const double2*)coef + (int64_t)g * D * ldc, ldc, Nmax, tb.perm, tb.Nr, basis,
+                               (double*)cg);
+            prof_end("k_pair_fp64", st);
+        }
+    }
+    if (corr) {
+        prof_begin("k_pair_var", st);
+        if (prec == MM_MIXED)
+            hipLaunchKernelGGL((k_pair_var<float2, float>), dim3(D, G), dim3(64), 0, st, D, (const float2*)coef, ldc,
+                               tb.perm, tb.Nr, tb.cutq, nq, basis, (float*)(ws + s.var));
+        else
+            hipLaunchKernelGGL((k_pair_var<double2, double>), dim3(D, G), dim3(64), 0, st, D, (const double2*)coef,
+                               ldc, tb.perm, tb.Nr, tb.cutq, nq, basis, (double*)(ws + s.var));
+        prof_end("k_pair_var", st);
+        const int64_t total = (int64_t)G * D * D;
+        const int blocks = (int)((total + 255) / 256);
+        prof_begin("k_pair_corr", st);
+        if (prec == MM_MIXED)
+            hipLaunchKernelGGL(k_pair_corr<float>, dim3(blocks), dim3(256), 0, st, total, D, tb.rank, tb.slot,
+                               (const float*)(ws + s.var), nq, (const float*)cov, (float*)corr);
+        else
+            hipLaunchKernelGGL(k_pair_corr<double>, dim3(blocks), dim3(256), 0, st, total, D, tb.rank, tb.slot,
+                               (const double*)(ws + s.var), nq, (const double*)cov, (double*)corr);
+        prof_end("k_pair_corr", st);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_cov_mfma(int32_t G, int32_t D, const void* coef, int64_t ldc, int32_t N, int basis, void* cov,
                            char* ws, hipStream_t st, bool operands_ready)
 {
@@ -832,19 +1118,19 @@ hipError_t launch_cov_mfma(int32_t G, int32_t D, const void* coef, int64_t ldc, 
         const char* syrk_name = s.ts == T2 ? "k_syrk_mfma256" : "k_syrk_mfma";
         prof_begin(syrk_name, st);
         if (s.ts == T2)
-            hipLaunchKernelGGL(k_syrk_mfma256, dim3((unsigned)(s.ntiles * s.nsplit)), dim3(256), 0, st, hi, lo, s.Kp,
-                               s.kchunk, s.ntiles, s.nsplit, part);
+            hipLaunchKernelGGL(k_syrk_mfma256, dim3((unsigned)(s.ntiles * s.nsplit)), dim3(256), 0, st, hi, lo, hi, lo,
+                               s.Kp, s.kchunk, s.ntiles, s.nsplit, part);
         else
-            hipLaunchKernelGGL(k_syrk_mfma, dim3((unsigned)(s.ntiles * s.nsplit)), dim3(256), 0, st, hi, lo, s.Kp,
-                               s.kchunk, s.ntiles, s.nsplit, part);
+            hipLaunchKernelGGL(k_syrk_mfma, dim3((unsigned)(s.ntiles * s.nsplit)), dim3(256), 0, st, hi, lo, hi, lo,
+                               s.Kp, s.kchunk, s.ntiles, s.nsplit, part);
         prof_end(syrk_name, st);
         prof_begin("k_syrk_reduce", st);
         if (s.ts == T2)
             hipLaunchKernelGGL(k_syrk_reduce<T2>, dim3((unsigned)(64 * s.ntiles)), dim3(256), 0, st, part, s.nsplit,
-                               s.ntiles, D, (float*)cov + (int64_t)g * D * D);
+                               s.ntiles, D, (float*)cov + (int64_t)g * D * D, (const int32_t*)nullptr);
         else
             hipLaunchKernelGGL(k_syrk_reduce<ST>, dim3((unsigned)(16 * s.ntiles)), dim3(256), 0, st, part, s.nsplit,
-                               s.ntiles, D, (float*)cov + (int64_t)g * D * D);
+                               s.ntiles, D, (float*)cov + (int64_t)g * D * D, (const int32_t*)nullptr);
         prof_end("k_syrk_reduce", st);
     }
     return hipGetLastError();

@@ -199,6 +199,19 @@ SplitOut cov_mfma_split_out(int32_t D, int32_t N, char* ws);
 hipError_t launch_split_prologue(int32_t D, int32_t N, int basis, char* ws, hipStream_t st);
 hipError_t launch_cov_fp64(int32_t G, int32_t D, const void* coef, int64_t ldc, int32_t N, int basis,
                            void* cov, hipStream_t st);
+// The one-pass per-pair-cutoff product (mm_cov_pairwise beyond the small-D path):
+// device tables of the rows in ascending-cutoff order.
+struct PairTables {
+    const int32_t* perm;   // [D] series of sorted row r
+    const int32_t* Nr;     // [D] cutoff of sorted row r
+    const int32_t* rank;   // [D] sorted row of series a
+    const int32_t* slot;   // [D] index of Nr[r] among the distinct cutoffs
+    const int32_t* cutq;   // [Nmax + 1] index of k among the distinct cutoffs, -1 if none
+};
+size_t cov_pair_workspace(int prec, int32_t G, int32_t D, int32_t Nmax, int32_t nq);
+hipError_t launch_cov_pair(int prec, int32_t G, int32_t D, const void* coef, int64_t ldc, int32_t Nmax,
+                           const PairTables& tb, int32_t nq, int basis, void* cov, void* corr, char* ws,
+                           hipStream_t st);
 
 // Optional per-kernel timing with HIP events on the launch stream.
 void prof_begin(const char* name, hipStream_t st);

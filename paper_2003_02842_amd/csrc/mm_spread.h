@@ -43,14 +43,8 @@ struct SpreadLds {
     static constexpr size_t bytes = 4 * (size_t)ring_floats + 2 * (size_t)EC + 2 * (size_t)first_len;
 };
 
-// Sources of the returns: a typed array, or an array whose type (FP32 or FP64) is
-// known only at run time (one uniform branch per load).
-template <typename T>
-struct DpPtr {
-    using V = T;
-    const T* __restrict__ p;
-    __device__ V operator[](int64_t i) const { return p[i]; }
-};
+// The returns as an array whose type (FP32 or FP64) is known only at run time (one
+// uniform branch per load).
 struct DpAny {
     using V = double;
     const void* p;
