@@ -68,9 +68,9 @@ def parse():
 PROFILE_TRAFFIC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "hbm_traffic.large-universe.md")
 
 
-def source_hash() -> str:
+def source_hash(tune=None) -> str:
     """First 16 hex digits of the SHA-256 over the library's kernel sources and
-    the tuned plan the default run uses."""
+    the plan (mm_tuning dict) the default run uses."""
     import hashlib
 
     from paper_2003_02842_amd.build import CSRC, HEADERS, SOURCES
@@ -78,22 +78,21 @@ def source_hash() -> str:
     for f in sorted(SOURCES + HEADERS):
         with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(fh.read())
-    from paper_2003_02842_amd.tune import LARGE_UNIVERSE
-    h.update(repr(sorted(LARGE_UNIVERSE.items())).encode())
+    h.update(repr(sorted((tune or {}).items())).encode())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str):
+def measured_traffic(kernel: str, tune=None):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE summary of the default workload, or None when that summary is
-    missing or was taken on other kernel sources."""
+    missing or was taken on other kernel sources or another plan."""
     try:
         with open(PROFILE_TRAFFIC) as fh:
             text = fh.read()
     except OSError:
         return None
     tag = "source_sha256_16: "
-    if tag not in text or text.split(tag, 1)[1].split()[0] != source_hash():
+    if tag not in text or text.split(tag, 1)[1].split()[0] != source_hash(tune):
         return None
     for line in text.splitlines():
         cells = [c.strip() for c in line.strip().strip("|").split("|")]
@@ -376,8 +375,9 @@ def main():
     E, S, N, D = w.E, w.S, a.N, a.D
     print("# generated %d events in %.1f s" % (E, t_gen), file=sys.stderr, flush=True)
 
-    from paper_2003_02842_amd.tune import LARGE_UNIVERSE
-    tune = {} if a.untuned else dict(LARGE_UNIVERSE)
+    from paper_2003_02842_amd.tune import LARGE_UNIVERSE, load_tuned
+    cached = None if a.untuned else load_tuned("large-universe")
+    tune = {} if a.untuned else dict(cached or LARGE_UNIVERSE)
     tune.update({k: v for k, v in (("width", a.width), ("sigma", a.sigma)) if v})
     tune = tune or None
     plan = mm.plan_query(N, a.kernel, a.tol, "mixed", tune)
@@ -440,7 +440,7 @@ def main():
     dom = max(kern, key=lambda k: kern[k]["avg_ms"])
     default_workload = (a.D, a.n_lo, a.n_hi, a.N, a.kernel, a.tol, a.basis, a.seed, a.width, a.sigma, a.untuned) == \
         (2000, 1e4, 1e6, 50_000, "es", 1e-6, "fejer", 20200310, 0, 0.0, False)
-    traffic = measured_traffic(dom) if default_workload else None
+    traffic = measured_traffic(dom, tune) if default_workload else None
     Mr = plan["Mr"]
     alg_bytes = {
         role["spread"]: E * (8 + 4) + S * Mr * 4 + (S + 1) * 8,
@@ -484,7 +484,8 @@ def main():
         "config": {"workload": "large-universe: D=%d 3-factor GBM, log-uniform counts [%g, %g], T=28800 s, N=%d, "
                                "%s kernel, %s basis" % (D, a.n_lo, a.n_hi, N, a.kernel, a.basis),
                    "events": E, "series": S, "N": N, "tol": a.tol, "width": plan["width"], "sigma": plan["sigma"], "Mr": Mr,
-                   "tuning": tune,
+                   "tuning": tune, "tuning_source": ("none" if a.untuned else
+                                                     "tuned_plans.json" if cached else "built-in default"),
                    "seed": a.seed, "parallelism": "1 GPU"},
         "nufft1_ms": t_nufft,
         "nufft1_events_per_s": E / (t_nufft * 1e-3) if t_nufft else None,

@@ -81,6 +81,10 @@ typedef struct {
                                   pair; 2 uses per-tap polynomials (fitted within tol/20) evaluated once per
                                   event; 0 (auto): polynomials for Kaiser-Bessel and ES, the formula for the
                                   Gaussian */
+    int32_t syrk_tile;         /* MM_MIXED contraction on MFMA (D(D+1)/2 > 1024): output tile edge, 128 or 256;
+                                  0: the built-in model (256 for large D and long k ranges) */
+    int32_t syrk_splits;       /* ... and the number of k-ranges each tile's sum is split into (partial tiles
+                                  summed afterwards), >= 1, at most one per 32 real columns; 0: the model */
 } mm_tuning;
 
 /* What the planner chose (host only, no device work). */
@@ -141,9 +145,9 @@ mm_status mm_nufft1(int32_t S, const int64_t* offsets, const double* t, const vo
                     const mm_tuning* tune, void* coef, int64_t ldc, void* ws, size_t ws_bytes,
                     int32_t validate, void* stream);
 
-/* Bytes of device workspace mm_cov needs (may be 0). */
+/* Bytes of device workspace mm_cov needs (may be 0); `tune` as for mm_cov. */
 mm_status mm_cov_workspace_size(int32_t G, int32_t D, int32_t Nmax, int32_t nN, mm_prec prec,
-                                size_t* bytes /* host */);
+                                const mm_tuning* tune, size_t* bytes /* host */);
 
 /* Dirichlet or Fejer estimates (Eqs. Der:2, Der:3; MM algorithm steps C.1/C.2)
  * and correlations (MM algorithm, last step) for G groups of D consecutive
@@ -154,10 +158,12 @@ mm_status mm_cov_workspace_size(int32_t G, int32_t D, int32_t Nmax, int32_t nN, 
  *   cov      nN x G x D x D, row-major: float (MM_MIXED) or double (MM_PLAIN_FP64).
  *   corr     same shape and type, or NULL.  R_ij is NaN where Sigma_ii <= 0 or
  *            Sigma_jj <= 0 (an empty series).
+ *   tune     NULL, or the contraction's tile and k-split (mm_tuning.syrk_tile, syrk_splits;
+ *            the other fields are ignored here)
  * Errors: MM_ERR_ARG, MM_ERR_WORKSPACE, MM_ERR_UNSUPPORTED, MM_ERR_HIP. */
 mm_status mm_cov(int32_t G, int32_t D, const void* coef, int64_t ldc, const int32_t* Ns, int32_t nN,
-                 mm_basis basis, mm_prec prec, void* cov, void* corr, void* ws, size_t ws_bytes,
-                 void* stream);
+                 mm_basis basis, mm_prec prec, const mm_tuning* tune, void* cov, void* corr, void* ws,
+                 size_t ws_bytes, void* stream);
 
 /* Bytes of device workspace mm_estimate needs for G*D series and the cutoffs Ns
  * (host int32[nN]): room for the coefficients at k = 0..max(Ns), the NUFFT

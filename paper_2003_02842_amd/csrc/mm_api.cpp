@@ -110,7 +110,7 @@ static int small_d_limit(int32_t D) { return (int64_t)D * (D + 1) / 2 <= 1024; }
 // The contraction for every cutoff, then the correlation (host checks already done).
 static hipError_t enqueue_cov(int32_t G, int32_t D, const void* coef, int64_t ldc, const int32_t* Ns, int32_t nN,
                               int32_t Nmax, mm_basis basis, mm_prec prec, void* cov, void* corr, char* ws,
-                              hipStream_t st, bool operands_ready = false)
+                              hipStream_t st, bool operands_ready = false, SyrkChoice sc = {})
 {
     hipError_t e = hipSuccess;
     const size_t es = prec == MM_MIXED ? 4 : 8;
@@ -123,7 +123,7 @@ static hipError_t enqueue_cov(int32_t G, int32_t D, const void* coef, int64_t ld
         for (int q = 0; q < nN && e == hipSuccess; ++q) {
             char* cq = (char*)cov + (size_t)q * G * D * D * es;
             if (prec == MM_MIXED)
-                e = launch_cov_mfma(G, D, coef, ldc, Ns[q], basis, cq, ws, st, operands_ready);
+                e = launch_cov_mfma(G, D, coef, ldc, Ns[q], basis, cq, ws, st, operands_ready, sc);
             else
                 e = launch_cov_fp64(G, D, coef, ldc, Ns[q], basis, cq, st);
         }
@@ -213,18 +213,21 @@ mm_status mm_nufft1(int32_t S, const int64_t* offsets, const double* t, const vo
     return hip_status(enqueue_nufft(p, w, wsb, S, offsets, t, dp, dp_is_fp64, t0, T, coef, ldc, st));
 }
 
-mm_status mm_cov_workspace_size(int32_t G, int32_t D, int32_t Nmax, int32_t nN, mm_prec prec, size_t* bytes)
+mm_status mm_cov_workspace_size(int32_t G, int32_t D, int32_t Nmax, int32_t nN, mm_prec prec, const mm_tuning* tune,
+                                size_t* bytes)
 {
     if (!bytes || G < 1 || D < 1 || Nmax < 1 || nN < 1 || nN > kMaxCutoffs) return MM_ERR_ARG;
     if (prec != MM_PLAIN_FP64 && prec != MM_MIXED) return MM_ERR_ARG;
-    *bytes = (small_d_limit(D) || prec == MM_PLAIN_FP64) ? 0 : cov_mfma_workspace(G, D, Nmax);
+    if (!syrk_choice_ok(tune)) return MM_ERR_ARG;
+    *bytes = (small_d_limit(D) || prec == MM_PLAIN_FP64) ? 0 : cov_mfma_workspace(G, D, Nmax, syrk_choice(tune));
     return MM_OK;
 }
 
 mm_status mm_cov(int32_t G, int32_t D, const void* coef, int64_t ldc, const int32_t* Ns, int32_t nN, mm_basis basis,
-                 mm_prec prec, void* cov, void* corr, void* ws, size_t ws_bytes, void* stream)
+                 mm_prec prec, const mm_tuning* tune, void* cov, void* corr, void* ws, size_t ws_bytes, void* stream)
 {
     if (G < 1 || D < 1 || !coef || !cov || !Ns || nN < 1 || nN > kMaxCutoffs) return MM_ERR_ARG;
+    if (!syrk_choice_ok(tune)) return MM_ERR_ARG;
     if (basis != MM_DIRICHLET && basis != MM_FEJER) return MM_ERR_ARG;
     if (prec != MM_PLAIN_FP64 && prec != MM_MIXED) return MM_ERR_ARG;
     if ((int64_t)G * D > 65535ll * 65535ll) return MM_ERR_UNSUPPORTED;
@@ -234,12 +237,12 @@ mm_status mm_cov(int32_t G, int32_t D, const void* coef, int64_t ldc, const int3
         Nmax = std::max(Nmax, Ns[q]);
     }
     size_t need = 0;
-    mm_cov_workspace_size(G, D, Nmax, nN, prec, &need);
+    mm_cov_workspace_size(G, D, Nmax, nN, prec, tune, &need);
     if (need > 0 && (!ws || ws_bytes < need)) return MM_ERR_WORKSPACE;
     if (need > 0 && ((uintptr_t)ws & 255) != 0) return MM_ERR_ARG;
     if (small_d_limit(D) && G > 65535) return MM_ERR_UNSUPPORTED;
     return hip_status(enqueue_cov(G, D, coef, ldc, Ns, nN, Nmax, basis, prec, cov, corr, (char*)ws,
-                                  (hipStream_t)stream));
+                                  (hipStream_t)stream, false, syrk_choice(tune)));
 }
 
 }  // extern "C"
@@ -252,12 +255,12 @@ struct EstLayout {
 
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-EstLayout est_layout(const Plan& p, int32_t S, int32_t G, int32_t D, int32_t Nmax, int32_t nN)
+EstLayout est_layout(const Plan& p, int32_t S, int32_t G, int32_t D, int32_t Nmax, int32_t nN, const mm_tuning* tune)
 {
     EstLayout L;
     const size_t cs = p.prec == MM_MIXED ? 8 : 16;
     size_t cw = 0;
-    mm_cov_workspace_size(G, D, Nmax, nN, (mm_prec)p.prec, &cw);
+    mm_cov_workspace_size(G, D, Nmax, nN, (mm_prec)p.prec, tune, &cw);
     L.coef = 0;
     L.nufft = al256((size_t)S * (size_t)(Nmax + 1) * cs);
     L.cov = L.nufft + al256(nufft_workspace(p, S).total);
@@ -293,7 +296,8 @@ mm_status mm_estimate_workspace_size(int32_t G, int32_t D, const int32_t* Ns, in
     Plan p;
     mm_status s = make_plan(Nmax, kernel, tol, prec, tune, &p);
     if (s != MM_OK) return s;
-    *bytes = est_layout(p, G * D, G, D, Nmax, nN).total;
+    if (!syrk_choice_ok(tune)) return MM_ERR_ARG;
+    *bytes = est_layout(p, G * D, G, D, Nmax, nN, tune).total;
     return MM_OK;
 }
 
@@ -317,8 +321,10 @@ mm_status mm_estimate(int32_t G, int32_t D, const int64_t* offsets, const double
     Plan p;
     mm_status s = make_plan(Nmax, kernel, tol, prec, tune, &p);
     if (s != MM_OK) return s;
+    if (!syrk_choice_ok(tune)) return MM_ERR_ARG;
+    const SyrkChoice sc = syrk_choice(tune);
     const int32_t S = G * D;
-    const EstLayout L = est_layout(p, S, G, D, Nmax, nN);
+    const EstLayout L = est_layout(p, S, G, D, Nmax, nN, tune);
     if (!ws || ws_bytes < L.total) return MM_ERR_WORKSPACE;
     if (((uintptr_t)ws & 255) != 0) return MM_ERR_ARG;
     char* wsb = (char*)ws;
@@ -334,17 +340,17 @@ mm_status mm_estimate(int32_t G, int32_t D, const int64_t* offsets, const double
     // values, rounded the same way, as the split step would).
     const bool fuse = !coef_out && G == 1 && nN == 1 && prec == MM_MIXED && !use_fused(p, S) && p.fft_ab &&
                       !small_d_limit(D);
-    const SplitOut so = fuse ? cov_mfma_split_out(D, Ns[0], wsb + L.cov) : SplitOut{nullptr, nullptr, 0, nullptr};
+    const SplitOut so = fuse ? cov_mfma_split_out(D, Ns[0], wsb + L.cov, sc) : SplitOut{nullptr, nullptr, 0, nullptr};
     auto enqueue = [&]() -> hipError_t {
         hipError_t e = hipSuccess;
         if (fuse) {
-            e = launch_split_prologue(D, Ns[0], basis, wsb + L.cov, st);
+            e = launch_split_prologue(D, Ns[0], basis, wsb + L.cov, st, sc);
             if (e != hipSuccess) return e;
         }
         e = enqueue_nufft(p, w, wsb + L.nufft, S, offsets, t, dp, dp_is_fp64, t0, T, coef, ldc, st,
                           fuse ? &so : nullptr);
         if (e != hipSuccess) return e;
-        return enqueue_cov(G, D, coef, ldc, Ns, nN, Nmax, basis, prec, cov, corr, wsb + L.cov, st, fuse);
+        return enqueue_cov(G, D, coef, ldc, Ns, nN, Nmax, basis, prec, cov, corr, wsb + L.cov, st, fuse, sc);
     };
     if (!use_graph) return hip_status(enqueue());
 
@@ -355,9 +361,9 @@ mm_status mm_estimate(int32_t G, int32_t D, const int64_t* offsets, const double
     put(key, basis); put(key, kernel); put(key, tol); put(key, prec); put(key, ldc); put(key, ws_bytes);
     put(key, coef_out);
     put(key, ptrs);
-    const mm_tuning tz = tune ? *tune : mm_tuning{0, 0.0, 0, 0, 0.0, 0, 0};
+    const mm_tuning tz = tune ? *tune : mm_tuning{0, 0.0, 0, 0, 0.0, 0, 0, 0, 0};
     put(key, tz.width); put(key, tz.sigma); put(key, tz.tile); put(key, tz.fused); put(key, tz.es_beta_per_tap);
-    put(key, tz.fft_generic); put(key, tz.spread_direct);
+    put(key, tz.fft_generic); put(key, tz.spread_direct); put(key, tz.syrk_tile); put(key, tz.syrk_splits);
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return MM_ERR_HIP;
     put(key, dev);
@@ -474,7 +480,7 @@ static size_t pairwise_layout(int32_t G, int32_t D, int32_t Nmax, int32_t nq, mm
     }
     const size_t es = prec == MM_MIXED ? 4 : 8;
     size_t cw = 0;
-    mm_cov_workspace_size(G, D, Nmax, nq, prec, &cw);
+    mm_cov_workspace_size(G, D, Nmax, nq, prec, nullptr, &cw);
     *sweep_off = al(4 * (size_t)D);
     *cov_off = *sweep_off + al((size_t)nq * G * D * D * es);
     return *cov_off + al(cw);

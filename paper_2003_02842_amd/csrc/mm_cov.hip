@@ -889,7 +889,7 @@ static int split_count(int ntiles, int64_t Kp)
     return best_s;
 }
 
-static MfmaShape mfma_shape(int32_t D, int32_t N)
+static MfmaShape mfma_shape(int32_t D, int32_t N, SyrkChoice sc = {})
 {
     MfmaShape s;
     s.Kp = ((2ll * (N + 1) + SK - 1) / SK) * SK;
@@ -897,14 +897,17 @@ static MfmaShape mfma_shape(int32_t D, int32_t N)
     // the 256-wide kernel addresses a panel with 32-bit byte offsets (row x Kp x 2 for
     // rows < 256, plus the k offset); beyond that the 128-wide kernel (64-bit) runs
     const bool offsets32 = (s.Kp * 2) * 257 < (1ll << 32);
-    if (MM_SYRK_BIG_TILES && tn2 >= 4 && s.Kp / SK2 >= 64 && offsets32) {
+    const bool big = sc.tile == 256 ? offsets32
+                   : sc.tile == 128 ? false
+                                    : (MM_SYRK_BIG_TILES && tn2 >= 4 && s.Kp / SK2 >= 64 && offsets32);
+    if (big) {
         // 256-wide tiles, about one workgroup per CU, so every tile's k-range runs
         // concurrently and the partials stay few
         s.ts = T2;
         s.tn = tn2;
         s.ntiles = s.tn * (s.tn + 1) / 2;
         s.Dp = (int64_t)s.tn * T2;
-        s.nsplit = split_count(s.ntiles, s.Kp);
+        s.nsplit = sc.splits > 0 ? (int)std::min<int64_t>(sc.splits, s.Kp / SK2) : split_count(s.ntiles, s.Kp);
         const int64_t per = (s.Kp + s.nsplit - 1) / s.nsplit;
         s.kchunk = ((per + SK2 - 1) / SK2) * SK2;
         auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
@@ -928,7 +931,7 @@ static MfmaShape mfma_shape(int32_t D, int32_t N)
     const int max_m = (int)std::max<int64_t>(1, ksteps / 64);
     best_m = std::max(1, std::min(best_m, max_m));
     // never more ranges than k-stages (an empty range would still write a partial tile)
-    s.nsplit = (int)std::min<int64_t>(8 * best_m, ksteps);
+    s.nsplit = (int)std::min<int64_t>(sc.splits > 0 ? sc.splits : 8 * best_m, ksteps);
     int64_t per = (s.Kp + s.nsplit - 1) / s.nsplit;
     s.kchunk = ((per + SK - 1) / SK) * SK;
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
@@ -941,10 +944,10 @@ static MfmaShape mfma_shape(int32_t D, int32_t N)
     return s;
 }
 
-size_t cov_mfma_workspace(int32_t G, int32_t D, int32_t Nmax)
+size_t cov_mfma_workspace(int32_t G, int32_t D, int32_t Nmax, SyrkChoice sc)
 {
     (void)G;
-    return mfma_shape(D, Nmax).total;
+    return mfma_shape(D, Nmax, sc).total;
 }
 
 // Zero padding of the split operands when the row pass writes them: the pairs
@@ -961,9 +964,9 @@ __global__ void k_split_pad(int D, int Dp, int N, int64_t kp2, uint32_t* __restr
     }
 }
 
-SplitOut cov_mfma_split_out(int32_t D, int32_t N, char* ws)
+SplitOut cov_mfma_split_out(int32_t D, int32_t N, char* ws, SyrkChoice sc)
 {
-    const MfmaShape s = mfma_shape(D, N);
+    const MfmaShape s = mfma_shape(D, N, sc);
     SplitOut o;
     o.hi = (uint32_t*)(ws + s.hi);
     o.lo = (uint32_t*)(ws + s.lo);
@@ -972,9 +975,9 @@ SplitOut cov_mfma_split_out(int32_t D, int32_t N, char* ws)
     return o;
 }
 
-hipError_t launch_split_prologue(int32_t D, int32_t N, int basis, char* ws, hipStream_t st)
+hipError_t launch_split_prologue(int32_t D, int32_t N, int basis, char* ws, hipStream_t st, SyrkChoice sc)
 {
-    const MfmaShape s = mfma_shape(D, N);
+    const MfmaShape s = mfma_shape(D, N, sc);
     prof_begin("k_split_scale", st);
     hipLaunchKernelGGL(k_split_scale, dim3((unsigned)((s.Kp / 2 + 255) / 256)), dim3(256), 0, st, N, basis, s.Kp / 2,
                        (float*)(ws + s.scale));
@@ -1092,9 +1095,9 @@ hipError_t launch_cov_pair(int prec, int32_t G, int32_t D, const void* coef, int
 }
 
 hipError_t launch_cov_mfma(int32_t G, int32_t D, const void* coef, int64_t ldc, int32_t N, int basis, void* cov,
-                           char* ws, hipStream_t st, bool operands_ready)
+                           char* ws, hipStream_t st, bool operands_ready, SyrkChoice sc)
 {
-    MfmaShape s = mfma_shape(D, N);
+    MfmaShape s = mfma_shape(D, N, sc);
     uint16_t* hi = (uint16_t*)(ws + s.hi);
     uint16_t* lo = (uint16_t*)(ws + s.lo);
     float* part = (float*)(ws + s.partial);

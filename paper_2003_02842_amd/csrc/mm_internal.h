@@ -177,6 +177,18 @@ hipError_t launch_snap(int64_t E, const double* t, double t0, double T, int64_t 
 hipError_t launch_input_returns(int32_t D, int64_t E, int64_t* offsets, double* t, void* dp, int dp_fp64,
                                 int32_t* nyq, const InputWs& w, char* ws, hipStream_t st);
 
+// Shape of the MFMA contraction requested by a caller's tuning (mm_tuning.syrk_tile,
+// syrk_splits); 0 leaves the choice to the built-in model.
+struct SyrkChoice {
+    int tile = 0;
+    int splits = 0;
+};
+inline SyrkChoice syrk_choice(const mm_tuning* t) { return t ? SyrkChoice{t->syrk_tile, t->syrk_splits} : SyrkChoice{}; }
+inline bool syrk_choice_ok(const mm_tuning* t)
+{
+    return !t || ((t->syrk_tile == 0 || t->syrk_tile == 128 || t->syrk_tile == 256) && t->syrk_splits >= 0);
+}
+
 // Contraction launchers (mm_cov.hip).
 struct Cutoffs {
     int n;
@@ -185,18 +197,18 @@ struct Cutoffs {
 hipError_t launch_cov_small(int prec, int32_t G, int32_t D, const void* coef, int64_t ldc, int32_t Nmax,
                             const Cutoffs& cut, int basis, void* cov, hipStream_t st);
 hipError_t launch_corr(int prec, int64_t mats, int32_t D, const void* cov, void* corr, hipStream_t st);
-size_t cov_mfma_workspace(int32_t G, int32_t D, int32_t Nmax);
+size_t cov_mfma_workspace(int32_t G, int32_t D, int32_t Nmax, SyrkChoice sc = {});
 hipError_t launch_pairwise_select(int prec, int32_t G, int32_t D, const int32_t* qidx, const void* sweep, void* cov,
                                   void* corr, hipStream_t st);
 // operands_ready: the split operands were written by the NUFFT's row pass
 // (launch_split_prologue, then SplitOut), so the scale and split steps are skipped.
 hipError_t launch_cov_mfma(int32_t G, int32_t D, const void* coef, int64_t ldc, int32_t N, int basis,
-                           void* cov, char* ws, hipStream_t st, bool operands_ready = false);
+                           void* cov, char* ws, hipStream_t st, bool operands_ready = false, SyrkChoice sc = {});
 // The fused split for one group and one cutoff N of the MFMA contraction: the
 // operand pointers in its workspace, and a prologue that writes the column scale
 // table and zeroes the operands' padding (rows D..Dp-1, columns beyond N).
-SplitOut cov_mfma_split_out(int32_t D, int32_t N, char* ws);
-hipError_t launch_split_prologue(int32_t D, int32_t N, int basis, char* ws, hipStream_t st);
+SplitOut cov_mfma_split_out(int32_t D, int32_t N, char* ws, SyrkChoice sc = {});
+hipError_t launch_split_prologue(int32_t D, int32_t N, int basis, char* ws, hipStream_t st, SyrkChoice sc = {});
 hipError_t launch_cov_fp64(int32_t G, int32_t D, const void* coef, int64_t ldc, int32_t N, int basis,
                            void* cov, hipStream_t st);
 // The one-pass per-pair-cutoff product (mm_cov_pairwise beyond the small-D path):

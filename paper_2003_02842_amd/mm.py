@@ -46,7 +46,7 @@ class CsrInfo(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("width", ctypes.c_int32), ("sigma", ctypes.c_double), ("tile", ctypes.c_int32),
                 ("fused", ctypes.c_int32), ("es_beta_per_tap", ctypes.c_double), ("fft_generic", ctypes.c_int32),
-                ("spread_direct", ctypes.c_int32)]
+                ("spread_direct", ctypes.c_int32), ("syrk_tile", ctypes.c_int32), ("syrk_splits", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -70,8 +70,8 @@ def lib():
         L.mm_plan_query.argtypes = [i32, i32, f64, i32, P, P]
         L.mm_nufft1_workspace_size.argtypes = [i32, i32, i32, f64, i32, P, ctypes.POINTER(sz)]
         L.mm_nufft1.argtypes = [i32, P, P, P, i32, f64, f64, i32, i32, f64, i32, P, P, i64, P, sz, i32, P]
-        L.mm_cov_workspace_size.argtypes = [i32, i32, i32, i32, i32, ctypes.POINTER(sz)]
-        L.mm_cov.argtypes = [i32, i32, P, i64, P, i32, i32, i32, P, P, P, sz, P]
+        L.mm_cov_workspace_size.argtypes = [i32, i32, i32, i32, i32, P, ctypes.POINTER(sz)]
+        L.mm_cov.argtypes = [i32, i32, P, i64, P, i32, i32, i32, P, P, P, P, sz, P]
         L.mm_estimate_workspace_size.argtypes = [i32, i32, P, i32, i32, f64, i32, P, ctypes.POINTER(sz)]
         L.mm_estimate.argtypes = [i32, i32, P, P, P, i32, f64, f64, P, i32, i32, i32, f64, i32, P, P, i64, P, P, P,
                                   sz, i32, P]
@@ -188,15 +188,19 @@ def nufft1(offsets: torch.Tensor, t: torch.Tensor, dp: torch.Tensor, t0: float, 
     return out
 
 
-def cov_workspace_size(G: int, D: int, Nmax: int, nN: int, prec="fp64") -> int:
+def cov_workspace_size(G: int, D: int, Nmax: int, nN: int, prec="fp64", tune=None) -> int:
     out = ctypes.c_size_t(0)
+    t = _tuning(tune)
     _check(lib().mm_cov_workspace_size(int(G), int(D), int(Nmax), int(nN), _enum(prec, _PRECS, "precision"),
-                                       ctypes.byref(out)), "mm_cov_workspace_size")
+                                       ctypes.byref(t) if t is not None else None, ctypes.byref(out)),
+           "mm_cov_workspace_size")
     return int(out.value)
 
 
-def cov(coef: torch.Tensor, G: int, D: int, Ns, basis="dirichlet", correlation: bool = True, ws: torch.Tensor = None):
-    """Sigma (and R) of shape (len(Ns), G, D, D) from (G*D, >=max(Ns)+1) coefficients."""
+def cov(coef: torch.Tensor, G: int, D: int, Ns, basis="dirichlet", correlation: bool = True, ws: torch.Tensor = None,
+        tune=None):
+    """Sigma (and R) of shape (len(Ns), G, D, D) from (G*D, >=max(Ns)+1) coefficients;
+    ``tune`` may set the contraction's tile (syrk_tile) and k-split (syrk_splits)."""
     if coef.dtype == torch.complex64:
         p, rdt = MIXED, torch.float32
     elif coef.dtype == torch.complex128:
@@ -209,11 +213,13 @@ def cov(coef: torch.Tensor, G: int, D: int, Ns, basis="dirichlet", correlation: 
     arr = (ctypes.c_int32 * len(Ns))(*Ns)
     covt = torch.empty((len(Ns), G, D, D), dtype=rdt, device=coef.device)
     corrt = torch.empty_like(covt) if correlation else None
-    need = cov_workspace_size(G, D, max(Ns), len(Ns), "mixed" if p == MIXED else "fp64")
+    need = cov_workspace_size(G, D, max(Ns), len(Ns), "mixed" if p == MIXED else "fp64", tune)
     if ws is None or ws.numel() < need:
         ws = _workspace(need, coef.device)
+    tt = _tuning(tune)
     st = lib().mm_cov(int(G), int(D), _ptr(coef), coef.stride(0), arr, len(Ns), _enum(basis, _BASES, "basis"), p,
-                      _ptr(covt), _ptr(corrt), _ptr(ws), ws.numel() if ws is not None else 0, _stream())
+                      ctypes.byref(tt) if tt is not None else None, _ptr(covt), _ptr(corrt), _ptr(ws),
+                      ws.numel() if ws is not None else 0, _stream())
     _check(st, "mm_cov")
     return covt, corrt
 

@@ -1,6 +1,8 @@
-"""Autotuner of the mixed-precision NUFFT plan: oversampling factor sigma,
-spreading tile (cells per workgroup) and the FP32 spreading evaluation (kernel
-formula per pair or per-tap polynomials), timed on the caller's own data.
+"""Autotuner of the mixed-precision plan, timed on the caller's own data: for the
+NUFFT the oversampling factor sigma, spreading tile (cells per workgroup) and the
+FP32 spreading evaluation (kernel formula per pair or per-tap polynomials); for
+the MFMA contraction its output tile (128 or 256) and the number of k-ranges
+each tile's sum is split into.
 
 For each sigma the planner already picks the smallest kernel width whose
 a-priori error estimate meets tol (the width follows from sigma and tol), so the
@@ -9,6 +11,10 @@ a calibration subset of the series, the covariance built from its coefficients
 stays within ``sigma_tol`` (relative Frobenius) of the FP64 form at tol 1e-12;
 the fastest admitted candidate wins.  Results can be cached in a JSON file keyed
 by the device, the workload shape and the request.
+
+The plans tuned on an MI355X for the benchmark workloads are kept in
+``tuned_plans.json`` beside this file (``python -m paper_2003_02842_amd.tune``
+writes it); ``load_tuned`` returns the entry for a workload on the current device.
 """
 from __future__ import annotations
 
@@ -127,6 +133,50 @@ def autotune(offsets, t, dp, t0: float, T: float, N: int, kernel="es", tol: floa
     return dict(best, cached=False)
 
 
+TUNED_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_plans.json")
+SYRK_TILES = (128, 256)
+SYRK_SPLITS = (0, 1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16)
+
+
+def autotune_contraction(coef, D: int, N: int, basis="fejer", tiles=SYRK_TILES, splits=SYRK_SPLITS,
+                         reps: int = 5, verbose: bool = False) -> dict:
+    """Fastest (syrk_tile, syrk_splits) of mm_cov on the caller's coefficients at
+    cutoff N (one group of D series, MM_MIXED).  Every candidate computes the same
+    sums in another order; each is checked against the model's default shape
+    (relative Frobenius <= 1e-6) before its time counts."""
+    ws_need = max(mm.cov_workspace_size(1, D, N, 1, "mixed", {"syrk_tile": t, "syrk_splits": sp})
+                  for t in tiles for sp in splits)
+    ws = torch.empty(max(ws_need, 256), dtype=torch.uint8, device=coef.device)
+    ref, _ = mm.cov(coef, 1, D, [N], basis, correlation=False, ws=ws)
+    ref = ref.double()
+    results = []
+    for t in tiles:
+        for sp in splits:
+            tune = {"syrk_tile": int(t), "syrk_splits": int(sp)}
+            S, _ = mm.cov(coef, 1, D, [N], basis, correlation=False, ws=ws, tune=tune)
+            err = float(torch.linalg.norm((S.double() - ref).flatten()) / torch.linalg.norm(ref.flatten()))
+            if not err <= 1e-6:
+                continue
+            ms = _time_ms(lambda: mm.cov(coef, 1, D, [N], basis, correlation=False, ws=ws, tune=tune), reps)
+            results.append((ms, tune))
+            if verbose:
+                print("tune: contraction %s: %.3f ms" % (tune, ms), flush=True)
+    ms, tune = min(results, key=lambda r: r[0])
+    return dict(tune, ms=ms, candidates=len(results))
+
+
+def load_tuned(workload: str, path: str = TUNED_PATH):
+    """The tuned mm_tuning dict for `workload` on the current device from the
+    committed cache, or None when there is no entry."""
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        cache = json.load(fh)
+    dev = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "none"
+    entry = cache.get("%s|%s" % (dev, workload))
+    return dict(entry["tuning"]) if entry else None
+
+
 def main(argv=None):
     """Tune the large-universe workload (2000 series, log-uniform counts in
     [1e4, 1e6], N = 50,000, ES, tol 1e-6, Fejer) and print every candidate."""
@@ -139,10 +189,29 @@ def main(argv=None):
     ap.add_argument("--N", type=int, default=50_000)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--sigmas", default="1.5,1.55,1.6,1.65,1.75,2.0")
+    ap.add_argument("--out", default=TUNED_PATH, help="plan cache to add the large-universe entry to")
     a = ap.parse_args(argv)
     w = synth.large_universe(D=a.D, N=a.N, device="cuda")
-    best = autotune(w.offsets, w.t, w.dp, w.t0, w.T, a.N, "es", a.tol, "fejer", reps=a.reps, verbose=True)
-    print(json.dumps(best))
+    best = autotune(w.offsets, w.t, w.dp, w.t0, w.T, a.N, "es", a.tol, "fejer", reps=a.reps, verbose=True,
+                    sigmas=tuple(float(x) for x in a.sigmas.split(",")), tiles=(2048, 4096), evals=(2,))
+    coef = mm.nufft1(w.offsets, w.t, w.dp, w.t0, w.T, a.N, "es", a.tol, "mixed", best["tuning"])
+    con = autotune_contraction(coef, w.S, a.N, "fejer", reps=a.reps, verbose=True)
+    tuning = dict(best["tuning"], syrk_tile=con["syrk_tile"], syrk_splits=con["syrk_splits"])
+    entry = {"tuning": tuning, "nufft_ms": best["ms"], "contraction_ms": con["ms"], "width": best["width"],
+             "Mr": best["Mr"], "calib_err": best["calib_err"],
+             "candidates": {"nufft": best["candidates"], "contraction": con["candidates"]},
+             "workload": "large universe: D=%d, log-uniform counts [1e4, 1e6], N=%d, ES tol %g, Fejer" % (
+                 a.D, a.N, a.tol)}
+    cache = {}
+    if os.path.exists(a.out):
+        with open(a.out) as fh:
+            cache = json.load(fh)
+    cache["%s|large-universe" % torch.cuda.get_device_name(0)] = entry
+    with open(a.out, "w") as fh:
+        json.dump(cache, fh, indent=1, sort_keys=True)
+        fh.write("\n")
+    print(json.dumps(entry))
 
 
 if __name__ == "__main__":

@@ -30,6 +30,17 @@ def test_library_exports_every_declared_symbol():
     assert set(syms) == set(mm.EXPORTED)
 
 
+def test_contraction_tuning_changes_only_the_workspace_shape():
+    """The tile and k-split choices size the split-K partials; 0 keeps the model's."""
+    auto = mm.cov_workspace_size(1, 2000, 50_000, 1, "mixed")
+    assert mm.cov_workspace_size(1, 2000, 50_000, 1, "mixed", {"syrk_tile": 0, "syrk_splits": 0}) == auto
+    one = mm.cov_workspace_size(1, 2000, 50_000, 1, "mixed", {"syrk_tile": 256, "syrk_splits": 1})
+    eight = mm.cov_workspace_size(1, 2000, 50_000, 1, "mixed", {"syrk_tile": 256, "syrk_splits": 8})
+    assert one < eight and eight - one == 7 * 36 * 256 * 256 * 4     # 36 lower tiles of 256 x 256 FP32
+    small = mm.cov_workspace_size(1, 2000, 50_000, 1, "mixed", {"syrk_tile": 128, "syrk_splits": 1})
+    assert small != one
+
+
 def test_status_strings():
     for s in range(7):
         assert mm.lib().mm_status_string(s)
@@ -59,13 +70,14 @@ def test_nufft1_rejects_before_launch(kw, status):
 
 
 def _cov_raw(**kw):
-    a = dict(G=1, D=3, coef=1, ldc=11, Ns=[5], basis=0, prec=1, cov=1, corr=0, ws=0, wsb=0)
+    a = dict(G=1, D=3, coef=1, ldc=11, Ns=[5], basis=0, prec=1, tune=None, cov=1, corr=0, ws=0, wsb=0)
     a.update(kw)
     P = ctypes.c_void_p
     arr = (ctypes.c_int32 * max(1, len(a["Ns"])))(*a["Ns"]) if a["Ns"] is not None else None
     n = a.get("nN", len(a["Ns"]) if a["Ns"] is not None else 1)
-    return mm.lib().mm_cov(a["G"], a["D"], P(a["coef"]), a["ldc"], arr, n, a["basis"], a["prec"], P(a["cov"]),
-                           P(a["corr"]), P(a["ws"]), a["wsb"], None)
+    tune = ctypes.byref(mm._tuning(a["tune"])) if a["tune"] is not None else None
+    return mm.lib().mm_cov(a["G"], a["D"], P(a["coef"]), a["ldc"], arr, n, a["basis"], a["prec"], tune,
+                           P(a["cov"]), P(a["corr"]), P(a["ws"]), a["wsb"], None)
 
 
 @pytest.mark.parametrize("kw,status", [
@@ -74,6 +86,8 @@ def _cov_raw(**kw):
     (dict(Ns=None), mm.MM_ERR_ARG), (dict(nN=0), mm.MM_ERR_ARG), (dict(nN=129, Ns=[1] * 129), mm.MM_ERR_ARG),
     (dict(basis=2), mm.MM_ERR_ARG), (dict(prec=9), mm.MM_ERR_ARG),
     (dict(D=200, ldc=5001, Ns=[5000]), mm.MM_ERR_WORKSPACE),
+    (dict(tune={"syrk_tile": 64}), mm.MM_ERR_ARG), (dict(tune={"syrk_splits": -1}), mm.MM_ERR_ARG),
+    (dict(D=200, ldc=5001, Ns=[5000], tune={"syrk_tile": 128, "syrk_splits": 3}), mm.MM_ERR_WORKSPACE),
 ])
 def test_cov_rejects_before_launch(kw, status):
     assert _cov_raw(**kw) == status

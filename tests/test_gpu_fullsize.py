@@ -33,13 +33,13 @@ def universe(mm):
     bench.py times (mm_estimate with the split fused into the FFT's row pass) and
     must equal the two-call form's bit for bit; the coefficients for sampling
     come from mm_nufft1."""
-    from paper_2003_02842_amd.tune import LARGE_UNIVERSE
+    from paper_2003_02842_amd.tune import LARGE_UNIVERSE, load_tuned
     w = synth.large_universe(device="cuda")
     N = w.Ns[0]
-    coef = mm.nufft1(w.offsets, w.t, w.dp, w.t0, w.T, N, "es", 1e-6, "mixed", dict(LARGE_UNIVERSE))
-    cov2, corr2 = mm.cov(coef, 1, w.S, [N], "fejer")
-    cov, corr, ws = mm.estimate(w.offsets, w.t, w.dp, w.t0, w.T, 1, w.S, [N], "fejer", "es", 1e-6, "mixed",
-                                dict(LARGE_UNIVERSE))
+    tune = load_tuned("large-universe") or dict(LARGE_UNIVERSE)   # the plan bench.py runs
+    coef = mm.nufft1(w.offsets, w.t, w.dp, w.t0, w.T, N, "es", 1e-6, "mixed", tune)
+    cov2, corr2 = mm.cov(coef, 1, w.S, [N], "fejer", tune=tune)
+    cov, corr, ws = mm.estimate(w.offsets, w.t, w.dp, w.t0, w.T, 1, w.S, [N], "fejer", "es", 1e-6, "mixed", tune)
     torch.cuda.synchronize()
     assert torch.equal(cov, cov2) and torch.equal(torch.nan_to_num(corr), torch.nan_to_num(corr2))
     del cov2, corr2, ws

@@ -38,3 +38,26 @@ def test_autotune_cross_section(mm, tmp_path):
     So, Ro = oracle.cov(oracle.coeffs_batch(w.offsets, w.t, w.dp, w.t0, w.T, N), 1, 100, [N], oracle.FEJER)
     assert relfro(S.cpu().numpy(), So) <= 1e-5
     assert relfro(R.cpu().numpy(), Ro) <= 1e-5
+
+
+@pytest.mark.parametrize("D,N", [(300, 3000), (1100, 2100)])
+def test_autotune_contraction(mm, D, N):
+    """The contraction tuner picks a (tile, k-split) from its candidate set; the
+    estimate at that shape meets the bar against the oracle (128-wide tiles at
+    D = 300, both widths at D = 1100)."""
+    from paper_2003_02842_amd import tune
+    rng = np.random.default_rng(D)
+    k = np.arange(N + 1)
+    c = ((rng.normal(size=(D, N + 1)) + 1j * rng.normal(size=(D, N + 1))) / np.sqrt(1 + k / 50.0)).astype(np.complex64)
+    c[:, 0] = c[:, 0].real
+    cd = torch.from_numpy(c).cuda()
+    best = tune.autotune_contraction(cd, D, N, "fejer", splits=(0, 1, 3, 7), reps=2)
+    assert best["syrk_tile"] in (128, 256) and best["syrk_splits"] in (0, 1, 3, 7) and best["candidates"] >= 4
+    S, R = mm.cov(cd, 1, D, [N], "fejer", tune={"syrk_tile": best["syrk_tile"], "syrk_splits": best["syrk_splits"]})
+    So, Ro = oracle.cov(c.astype(np.complex128), 1, D, [N], oracle.FEJER)
+    assert relfro(S.cpu().numpy(), So) <= 1e-5
+    assert relfro(R.cpu().numpy(), Ro) <= 1e-5
+    # every shape, including 256-wide tiles on few stages, gives the oracle's estimate
+    for t, sp in ((128, 1), (128, 5), (256, 1), (256, 4)):
+        S, _ = mm.cov(cd, 1, D, [N], "fejer", correlation=False, tune={"syrk_tile": t, "syrk_splits": sp})
+        assert relfro(S.cpu().numpy(), So) <= 1e-5, (t, sp)
