@@ -89,13 +89,29 @@ __global__ void k_cov_small(int D, const CT* __restrict__ coef, int64_t ldc, int
     double S0 = 0.0, S1 = 0.0, a0 = 0.0, a1 = 0.0;
     int q = 0;
     const double fourpi2 = kTwoPi * kTwoPi;
+    // the next chunk is loaded into registers (at most PF values per thread) while the
+    // current one is summed, so its loads are in flight during the arithmetic
+    constexpr int PF = 5;
+    CT nxt[PF];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            const int idx = (int)threadIdx.x + u * (int)blockDim.x;
+            const int d = idx / KC, kk = idx - d * KC;
+            if (idx < D * KC && k0 + kk <= Nmax) nxt[u] = coef[(int64_t)(g * D + d) * ldc + k0 + kk];
+            else nxt[u] = CT{0, 0};
+        }
+    };
+    fetch(0);
     for (int k0 = 0; k0 <= Nmax; k0 += KC) {
         const int kc = min(KC, Nmax + 1 - k0);
         __syncthreads();
-        for (int idx = threadIdx.x; idx < D * KC; idx += blockDim.x) {
-            const int d = idx / KC, kk = idx - d * KC;
-            sh[idx] = (kk < kc) ? to_d2(coef[(int64_t)(g * D + d) * ldc + k0 + kk]) : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            const int idx = (int)threadIdx.x + u * (int)blockDim.x;
+            if (idx < D * KC) sh[idx] = to_d2(nxt[u]);
         }
+        if (k0 + KC <= Nmax) fetch(k0 + KC);
         __syncthreads();
         int kk = 0;
         while (kk < kc) {
@@ -811,6 +827,7 @@ hipError_t launch_cov_small(int prec, int32_t G, int32_t D, const void* coef, in
     int kl_bits = 0;
     while (kl_bits < 6 && npairs * (2 << kl_bits) <= 512) ++kl_bits;
     const int threads = std::max(64, ((npairs << kl_bits) + 63) / 64 * 64);
+    if (D * 64 > 5 * threads) return hipErrorInvalidValue;   // k_cov_small stages at most 5 values per thread
     const size_t lds = (size_t)D * 64 * sizeof(double2);
     prof_begin("k_cov_small", st);
     if (prec == MM_MIXED)

@@ -74,3 +74,26 @@ def test_beyond_32bit_flat_index(mm):
     Rref = ref / np.sqrt(var[rows][:, None] * var[None, :])
     assert relfro(Rg, Rref) <= 1e-5
     np.testing.assert_allclose(diagR, 1.0, rtol=0, atol=1e-6)
+
+
+@pytest.mark.parametrize("D", [1, 5, 23, 44])
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_small_d_sweep_matches_oracle(mm, D, prec):
+    """The small-D sweep (one workgroup per group, running FP64 sums read off at
+    every cutoff) at the sizes that stage the most values per thread (D = 23) and
+    the largest D it takes (44), over three groups and five cutoffs, both bases."""
+    G, N = 3, 700
+    c = np.concatenate([random_coefficients(D, N, seed=D * 10 + g) for g in range(G)])
+    if prec == "fp64":
+        c = c.astype(np.complex128)
+    cd = torch.from_numpy(c).cuda()
+    Ns = [1, 17, 300, 301, 700]
+    for basis, b in (("dirichlet", oracle.DIRICHLET), ("fejer", oracle.FEJER)):
+        S, R = mm.cov(cd, G, D, Ns, basis)
+        So, Ro = oracle.cov(c.astype(np.complex128), G, D, Ns, b)
+        bar = 1e-5 if prec == "mixed" else 1e-11
+        S, R = S.cpu().numpy(), R.cpu().numpy()
+        for q in range(len(Ns)):
+            for g in range(G):
+                assert relfro(S[q, g], So[q, g]) <= bar, (D, Ns[q], g)
+                assert relfro(R[q, g], Ro[q, g]) <= bar, (D, Ns[q], g)
