@@ -496,7 +496,9 @@ mm_status make_plan(int32_t N, mm_kernel kernel, double tol, mm_prec prec, const
             p->poly_err = err;
         }
     }
-    p->est_err = estimate_error(p->kp, sg, p->Mr, N, (prec == MM_MIXED) ? rounding_gain(kernel, p->poly) : 0.0);
+    // the polynomials' own deviation from the kernel (relative to its peak, 1) adds to the bound
+    p->est_err = estimate_error(p->kp, sg, p->Mr, N, (prec == MM_MIXED) ? rounding_gain(kernel, p->poly) : 0.0) +
+                 (p->poly ? p->poly_err : 0.0);
     int tile = (prec == MM_MIXED) ? 2048 : 1024;
     if (tune && tune->tile > 0) tile = tune->tile <= 1024 ? 1024 : (tune->tile <= 2048 ? 2048 : 4096);
     p->tile = tile;
