@@ -103,7 +103,8 @@ typedef struct {
                                   kernel plus deconvolution mismatch (worst case over k); on the mixed path the
                                   FP32 rounding term 2^-24 G rms_k psi_hat(0)/psi_hat(k/Mr) instead when larger
                                   (G measured per evaluation: 2 polynomials, 4.5 ES, 6.5 Gaussian, 10
-                                  Kaiser-Bessel formula) */
+                                  Kaiser-Bessel formula), plus the per-tap polynomials' largest deviation
+                                  from the kernel where they are used */
 } mm_plan_info;
 
 /* Plan of a type-1 NUFFT of cutoff N (Sec. 2.2.5): the spreading width follows

@@ -23,7 +23,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["mm_plan.cpp", "mm_api.cpp", "mm_nufft.hip", "mm_fft.hip", "mm_cov.hip", "mm_input.hip", "mm_scratch.hip",
            "mm_fused.hip"]
-HEADERS = ["mm_bf16.h", "mm_internal.h", "mm_spread.h", "mm_fft_codelets.h"]
+HEADERS = ["mm_bf16.h", "mm_internal.h", "mm_layout.h", "mm_spread.h", "mm_fft_codelets.h"]
 # measurement probe for bench.py (not part of the estimator), its own library
 PEAK_SOURCE = "mm_peak.hip"
 PEAK_LIB = os.path.join(HERE, "libmm_peak.so")

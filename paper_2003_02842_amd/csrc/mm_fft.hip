@@ -223,32 +223,6 @@ __global__ void k_fft_tables(int L1, int L2, int L, int Mr, int lo_bits, int n_h
 }
 
 // ---------------------------------------------------------------- host side
-bool fft_ab_split(int n, int max_codelet, int* A, int* B)
-{
-    static const int sizes[] = {1, 2, 3, 4, 5, 6, 8, 9, 10, 12, 15, 16, 18, 20, 24, 25, 27, 30, 32};
-    int best = -1;
-    for (int a : sizes)
-        for (int b : sizes)
-            if (a * b == n && a <= b && b <= max_codelet && (best < 0 || b < best)) {
-                best = b;
-                *A = a;
-                *B = b;
-            }
-    return best > 0;
-}
-
-size_t fft_ab_lds_cols(const Plan& p)
-{
-    const size_t cs = p.prec == MM_MIXED ? 8 : 16;
-    return cs * ((size_t)p.L1 + (1u << p.tw_lo_bits) + p.tw_hi_L + (size_t)p.A1 * (p.B1 * p.CC + 1));
-}
-
-size_t fft_ab_lds_rows(const Plan& p)
-{
-    const size_t cs = p.prec == MM_MIXED ? 8 : 16;
-    return cs * ((size_t)p.L2 + (1u << p.tw_lo_bits) + p.tw_hi_M + 2 * (size_t)p.RR * (p.L2 + 1));
-}
-
 static int round64(int x) { return (x + 63) & ~63; }
 
 template <typename T>

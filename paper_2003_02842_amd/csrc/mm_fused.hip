@@ -22,39 +22,14 @@
 
 #include "mm_fft_codelets.h"
 #include "mm_internal.h"
+#include "mm_layout.h"
 #include "mm_spread.h"
 
 namespace mm {
 
-constexpr int kFusedThreads = 512;                                 // eight waves per series
-constexpr int kFusedPPT = kFusedMaxCells / (2 * kFusedThreads);    // cell pairs per thread
-constexpr int kFusedEV = 2;                                        // events per thread per staged chunk
-
 // Codelet sizes of the fused kernel's FFT steps: up to 16 points, which keeps the
 // register arrays of a step (and so the kernel's VGPRs) small.
 #define MM_CODELETS16(X) X(1) X(2) X(3) X(4) X(5) X(6) X(8) X(9) X(10) X(12) X(15) X(16)
-
-// LDS layout of k_nufft_fused in float2 units: tables, then the grid z (also the
-// row pass's output rows), then the exchange buffer sh.
-struct FusedLds {
-    int tw1, tw2, Llo, Lhi, Mlo, Mhi, z, sh, total;
-};
-__host__ __device__ inline FusedLds fused_lds(int L1, int L2, int A1, int B1, int lo_bits, int n_hi)
-{
-    FusedLds f;
-    const int LO = 1 << lo_bits, P = L1 / 2 + 1, rs = L2 + 1;
-    f.tw1 = 0;
-    f.tw2 = f.tw1 + L1;
-    f.Llo = f.tw2 + L2;
-    f.Lhi = f.Llo + LO;
-    f.Mlo = f.Lhi + n_hi;
-    f.Mhi = f.Mlo + LO;
-    f.z = (f.Mhi + n_hi + 1) & ~1;                       // 16-byte aligned
-    const int zlen = max(L1 * L2, 2 * P * rs);
-    f.sh = f.z + ((zlen + 1) & ~1);
-    f.total = f.sh + max(A1 * (B1 * L2 + 1), 2 * P * rs);
-    return f;
-}
 
 template <int W>
 __global__ __launch_bounds__(kFusedThreads) void k_nufft_fused(const double* __restrict__ t, DpAny dp,
@@ -180,37 +155,6 @@ __global__ __launch_bounds__(kFusedThreads) void k_nufft_fused(const double* __r
 }
 
 // Bytes of the spreading's rings, keys and cell index for a plan's width.
-static size_t fused_spread_bytes(int w)
-{
-    switch (w) {
-#define MM_SB(n) case n: return SpreadLds<n, kFusedPPT, kFusedThreads, kFusedEV>::bytes;
-        MM_SB(4) MM_SB(5) MM_SB(6) MM_SB(7) MM_SB(8) MM_SB(9) MM_SB(10) MM_SB(11) MM_SB(12)
-#undef MM_SB
-    }
-    return (size_t)1 << 30;
-}
-
-// Dynamic LDS of k_nufft_fused: the tables, then the larger of the grid plus
-// exchange buffer and the spreading's buffers (which lie over them).
-size_t fused_lds_bytes(const Plan& p)
-{
-    const FusedLds f = fused_lds(p.L1, p.L2, p.A1, p.B1, p.tw_lo_bits, p.tw_hi_L);
-    return std::max(8 * (size_t)f.total, 8 * (size_t)f.z + fused_spread_bytes(p.kp.w));
-}
-
-// Whether the fused kernel can run this plan: the mixed path with per-tap
-// polynomials of 4 to 12 taps (the widths compiled here), the two-pass codelet
-// FFT with sub-lengths of at most 16 points, a grid of at most kFusedMaxCells, and
-// its LDS within kFusedMaxLds.
-bool fused_fits(const Plan& p)
-{
-    if (p.prec != MM_MIXED || !p.poly || !p.fft_ab || p.Mr > kFusedMaxCells || p.kp.w < 4 || p.kp.w > 12)
-        return false;
-    if (p.B1 > 16 || p.B2 > 16) return false;   // codelets of the fused kernel: up to 16 points
-    if (p.tw_hi_L != p.tw_hi_M) return false;
-    return fused_lds_bytes(p) <= kFusedMaxLds;
-}
-
 template <int W>
 static void fused_w(const Plan& p, const NufftWs& w, char* ws, int32_t S, const double* t, DpAny dp,
                     double t0, double scale, const int64_t* ranges, float2* coef, int64_t ldc, hipStream_t st)

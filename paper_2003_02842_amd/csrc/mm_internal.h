@@ -118,6 +118,14 @@ mm_status make_plan(int32_t N, mm_kernel kernel, double tol, mm_prec prec, const
 uint64_t smooth_even_at_least(uint64_t n);
 FastDiv make_fastdiv(uint32_t d);
 void gauss_legendre_pos(int n_pos, double* x, double* w);   // nodes/weights on (0,1] of a 2n_pos rule on [-1,1]
+// What the planner checks against the kernels' LDS (layouts in mm_layout.h): the
+// codelet split n = A x B of a two-pass FFT and the LDS of its column and row
+// passes; whether the fused small-grid NUFFT can run a plan, and its LDS.
+bool fft_ab_split(int n, int max_codelet, int* A, int* B);
+size_t fft_ab_lds_cols(const Plan& p);
+size_t fft_ab_lds_rows(const Plan& p);
+bool fused_fits(const Plan& p);
+size_t fused_lds_bytes(const Plan& p);
 
 // Workspace layout of one mm_nufft1 call.
 struct NufftWs {
@@ -154,17 +162,12 @@ hipError_t launch_spread_poly(const Plan& p, int s_count, const double* t, const
 hipError_t launch_nufft_fused(const Plan& p, const NufftWs& w, char* ws, int32_t S, const int64_t* offsets,
                               const double* t, const void* dp, int dp_fp64, double t0, double T,
                               void* coef, int64_t ldc, hipStream_t st);
-bool fused_fits(const Plan& p);
-size_t fused_lds_bytes(const Plan& p);
 // Event ranges of every (series, tile of tc cells) (k_tile_ranges).
 hipError_t launch_tile_ranges(const Plan& p, const int64_t* offsets, const double* t, int32_t s_begin,
                               int32_t s_count, int tiles, int tc, double t0, double T, int64_t* ranges,
                               hipStream_t st);
 
 // Two-pass grid FFT with one LDS exchange per pass (mm_fft.hip).
-bool fft_ab_split(int n, int max_codelet, int* A, int* B);
-size_t fft_ab_lds_cols(const Plan& p);
-size_t fft_ab_lds_rows(const Plan& p);
 hipError_t launch_fft_ab_tables(const Plan& p, const NufftWs& w, char* ws, hipStream_t st);
 hipError_t launch_fft_ab(const Plan& p, const NufftWs& w, char* ws, int32_t s_begin, int32_t s_count, void* grid,
                          int64_t gstride, void* coef, int64_t ldc, hipStream_t st, const SplitOut* so = nullptr);

@@ -10,6 +10,7 @@
 #include <tuple>
 
 #include "mm_internal.h"
+#include "mm_layout.h"
 
 namespace mm {
 
@@ -377,6 +378,67 @@ static int msp_for_width(int kernel, int w)
     return (w + 1) / 2;
 }
 
+// Codelet split n = A x B (A <= B <= max_codelet, smallest B) of a two-pass
+// codelet FFT, and the LDS of its column and row passes.
+bool fft_ab_split(int n, int max_codelet, int* A, int* B)
+{
+    static const int sizes[] = {1, 2, 3, 4, 5, 6, 8, 9, 10, 12, 15, 16, 18, 20, 24, 25, 27, 30, 32};
+    int best = -1;
+    for (int a : sizes)
+        for (int b : sizes)
+            if (a * b == n && a <= b && b <= max_codelet && (best < 0 || b < best)) {
+                best = b;
+                *A = a;
+                *B = b;
+            }
+    return best > 0;
+}
+
+size_t fft_ab_lds_cols(const Plan& p)
+{
+    const size_t cs = p.prec == MM_MIXED ? 8 : 16;
+    return cs * ((size_t)p.L1 + (1u << p.tw_lo_bits) + p.tw_hi_L + (size_t)p.A1 * (p.B1 * p.CC + 1));
+}
+
+size_t fft_ab_lds_rows(const Plan& p)
+{
+    const size_t cs = p.prec == MM_MIXED ? 8 : 16;
+    return cs * ((size_t)p.L2 + (1u << p.tw_lo_bits) + p.tw_hi_M + 2 * (size_t)p.RR * (p.L2 + 1));
+}
+
+// LDS of the fused kernel's spreading buffers at width w (the widths it is built for)
+static size_t fused_spread_bytes(int w)
+{
+    switch (w) {
+#define MM_SB(n) case n: return SpreadLds<n, kFusedPPT, kFusedThreads, kFusedEV>::bytes;
+        MM_SB(4) MM_SB(5) MM_SB(6) MM_SB(7) MM_SB(8) MM_SB(9) MM_SB(10) MM_SB(11) MM_SB(12)
+#undef MM_SB
+    }
+    return (size_t)1 << 30;
+}
+
+// Dynamic LDS of k_nufft_fused: the tables, then the larger of the grid plus
+// exchange buffer and the spreading's buffers (which lie over them).
+size_t fused_lds_bytes(const Plan& p)
+{
+    const FusedLds f = fused_lds(p.L1, p.L2, p.A1, p.B1, p.tw_lo_bits, p.tw_hi_L);
+    return std::max(8 * (size_t)f.total, 8 * (size_t)f.z + fused_spread_bytes(p.kp.w));
+}
+
+// Whether the fused kernel can run this plan: the mixed path with per-tap
+// polynomials of 4 to 12 taps (the widths compiled here), the two-pass codelet
+// FFT with sub-lengths of at most 16 points, a grid of at most kFusedMaxCells, and
+// its LDS within kFusedMaxLds.
+bool fused_fits(const Plan& p)
+{
+    if (p.prec != MM_MIXED || !p.poly || !p.fft_ab || p.Mr > kFusedMaxCells || p.kp.w < 4 || p.kp.w > 12)
+        return false;
+    if (p.B1 > 16 || p.B2 > 16) return false;   // codelets of the fused kernel: up to 16 points
+    if (p.tw_hi_L != p.tw_hi_M) return false;
+    return fused_lds_bytes(p) <= kFusedMaxLds;
+}
+
+
 mm_status make_plan(int32_t N, mm_kernel kernel, double tol, mm_prec prec, const mm_tuning* tune, Plan* p)
 {
     memset(p, 0, sizeof(*p));
@@ -433,8 +495,11 @@ mm_status make_plan(int32_t N, mm_kernel kernel, double tol, mm_prec prec, const
             if (ma < 1) continue;
             set_kernel(q.kp, kernel, wa, ma, sg, tune);
             if (set_grid(&q) != MM_OK) continue;
-            const double gain = (prec == MM_MIXED) ? rounding_gain(kernel, want_poly && wa <= kMaxPolyTaps) : 0.0;
-            if (estimate_error(q.kp, sg, q.Mr, N, gain) <= tol) { found = true; break; }
+            // with per-tap polynomials their fit (admitted up to tol/20, below) takes
+            // its share of the bound
+            const bool pc = prec == MM_MIXED && want_poly && wa <= kMaxPolyTaps;
+            const double gain = (prec == MM_MIXED) ? rounding_gain(kernel, pc) : 0.0;
+            if (estimate_error(q.kp, sg, q.Mr, N, gain) + (pc ? 0.05 * tol : 0.0) <= tol) { found = true; break; }
         }
         if (!found) return MM_ERR_TOL;   // tol out of reach at this oversampling
         w = wa;

@@ -5,11 +5,8 @@
 #include <hip/hip_runtime.h>
 
 #include "mm_internal.h"
+#include "mm_layout.h"
 
-// Events staged per LDS chunk (a multiple of 256).
-#ifndef MM_POLY_CHUNK
-#define MM_POLY_CHUNK 512
-#endif
 
 namespace mm {
 
@@ -30,18 +27,8 @@ namespace mm {
 // spread_tile_poly runs both phases over the events of one tile [a, a + len) of
 // one series (rg: the tile's three event ranges, m = -1, 0, 1 periods away) with a
 // workgroup of NT threads, leaving cell pair (c, c+1), c = 2 (tid + NT r), in
-// acc0[r], acc1[r].  The LDS buffers are the caller's (SpreadLds sizes them).
-template <int W, int PPT, int NT = 256, int EV = 0>
-struct SpreadLds {
-    static constexpr int TC = 2 * NT * PPT;             // cells of a tile
-    static constexpr int M = (W + 2) & ~1;               // even ring, >= W + 1
-    static constexpr int EC0 = (M <= 12 || MM_POLY_CHUNK <= 256) ? MM_POLY_CHUNK : MM_POLY_CHUNK / 2;   // ~25 KB
-    // events per chunk, a multiple of NT: EV per thread if given, else about EC0
-    static constexpr int EC = EV > 0 ? EV * NT : (EC0 < NT ? NT : EC0);
-    static constexpr int ring_floats = EC * M;
-    static constexpr int first_len = TC + W + 2;
-    static constexpr size_t bytes = 4 * (size_t)ring_floats + 2 * (size_t)EC + 2 * (size_t)first_len;
-};
+// acc0[r], acc1[r].  The LDS buffers are the caller's (SpreadLds in mm_layout.h sizes
+// them).
 
 // The returns as an array whose type (FP32 or FP64) is known only at run time (one
 // uniform branch per load).

@@ -222,3 +222,25 @@ def test_estimate_workspace_covers_both_stages():
     nufft = mm.nufft1_workspace_size(G * D, max(Ns), "es", 1e-6, "mixed")
     coef = G * D * (max(Ns) + 1) * 8
     assert est >= nufft + coef + mm.cov_workspace_size(G, D, max(Ns), len(Ns), "mixed")
+
+
+def test_planner_under_address_and_undefined_behaviour_sanitizers(tmp_path):
+    """The planner (mm_plan.cpp) built for the host with ASan and UBSan plans ~19k
+    combinations of cutoff, kernel, tolerance, precision and tuning, valid and not,
+    and checks what every accepted plan promises (tests/plan_sanitize.cpp)."""
+    import shutil
+    import subprocess
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("no host C++ compiler")
+    csrc = os.path.join(ROOT, "paper_2003_02842_amd", "csrc")
+    exe = str(tmp_path / "plan_sanitize")
+    cmd = [gxx, "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+           "-fno-omit-frame-pointer", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-I", os.path.join(ROOT, "include"),
+           "-I", csrc, os.path.join(csrc, "mm_plan.cpp"), os.path.join(ROOT, "tests", "plan_sanitize.cpp"), "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-4000:]
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0", UBSAN_OPTIONS="print_stacktrace=1")
+    r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=300)
+    assert r.returncode == 0, (r.stdout[-4000:], r.stderr[-4000:])
+    assert "0 failed checks" in r.stdout and "ERROR" not in r.stderr and "runtime error" not in r.stderr
