@@ -253,7 +253,7 @@ def estimate_bench(a, workload):
     torch.cuda.synchronize()
     mm.profile_enable(False)
     kern_ms = {}
-    for nm in ("k_deconv", "k_fft_tables", "k_tile_ranges", "k_nufft_fused", "k_spread_poly", "k_spread", "k_fft_cols_ab",
+    for nm in ("k_setup", "k_prep", "k_deconv", "k_fft_tables", "k_tile_ranges", "k_nufft_fused", "k_spread_poly", "k_spread", "k_fft_cols_ab",
                "k_fft_rows_ab", "k_cov_small", "k_split_scale", "k_split_bf16", "k_syrk_mfma256", "k_syrk_mfma",
                "k_syrk_reduce", "k_corr"):
         t, n = mm.profile_read(nm)
@@ -412,7 +412,7 @@ def main():
     # kernel names as launched (the planner picks one kernel per role)
     roles = {"spread": ("k_spread_poly", "k_spread"), "fft_cols": ("k_fft_cols_ab", "k_fft_cols"),
              "fft_rows": ("k_fft_rows_ab", "k_fft_rows"), "syrk": ("k_syrk_mfma256", "k_syrk_mfma")}
-    names = ["k_prep", "k_deconv", "k_fft_tables", "k_tile_ranges", "k_split_scale", "k_split_pad", "k_split_bf16",
+    names = ["k_setup", "k_prep", "k_deconv", "k_fft_tables", "k_tile_ranges", "k_split_scale", "k_split_pad", "k_split_bf16",
              "k_syrk_reduce", "k_corr", "k_cov_small"] + \
         [n for r in roles.values() for n in r]
     kern = {}
@@ -426,7 +426,8 @@ def main():
           file=sys.stderr, flush=True)
 
     # the NUFFT's own kernels (mm_nufft1), summed
-    t_nufft = sum(kern[k]["avg_ms"] for k in ("k_prep", "k_deconv", "k_fft_tables", "k_tile_ranges", role["spread"],
+    t_nufft = sum(kern[k]["avg_ms"] for k in ("k_setup", "k_prep", "k_deconv", "k_fft_tables", "k_tile_ranges",
+                                                role["spread"],
                                                 role["fft_cols"], role["fft_rows"]) if k in kern)
     # contraction throughput (GEMM-equivalent flops)
     K = 2 * N + 1

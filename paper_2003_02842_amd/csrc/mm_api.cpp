@@ -90,14 +90,21 @@ static hipError_t enqueue_nufft(const Plan& p, const NufftWs& w, char* wsb, int3
                                 const double* t, const void* dp, int32_t dp_is_fp64, double t0, double T,
                                 void* coef, int64_t ldc, hipStream_t st, const SplitOut* so = nullptr)
 {
+    if (p.prec == MM_MIXED) {
+        // the tile ranges of every series come from the set-up launch when its
+        // grids are resident at once (the fused kernel: one whole-grid tile each)
+        const bool fz = use_fused(p, S);
+        if (fz && so) return hipErrorInvalidValue;
+        const bool one_pass = fz || S <= w.S_grid;
+        const RangeReq rr{offsets, t, 0, S, fz ? 1 : (p.Mr + p.tile - 1) / p.tile, fz ? kFusedMaxCells : p.tile, t0,
+                          T, (int64_t*)(wsb + w.ranges)};
+        hipError_t e = launch_prep(p, w, wsb, st, one_pass ? &rr : nullptr);
+        if (e != hipSuccess) return e;
+        if (fz) return launch_nufft_fused(p, w, wsb, S, t, dp, dp_is_fp64, t0, T, coef, ldc, st);
+        return launch_nufft_tiled(p, w, wsb, 0, S, offsets, t, dp, dp_is_fp64, t0, T, coef, ldc, st, so, one_pass);
+    }
     hipError_t e = launch_prep(p, w, wsb, st);
     if (e != hipSuccess) return e;
-    if (p.prec == MM_MIXED) {
-        if (use_fused(p, S))
-            return so ? hipErrorInvalidValue
-                      : launch_nufft_fused(p, w, wsb, S, offsets, t, dp, dp_is_fp64, t0, T, coef, ldc, st);
-        return launch_nufft_tiled(p, w, wsb, 0, S, offsets, t, dp, dp_is_fp64, t0, T, coef, ldc, st, so);
-    }
     if (so) return hipErrorInvalidValue;
     // plain form: one launch chain per series, grid buffer reused in stream order
     for (int32_t sidx = 0; sidx < S && e == hipSuccess; ++sidx)
@@ -118,7 +125,8 @@ static hipError_t enqueue_cov(int32_t G, int32_t D, const void* coef, int64_t ld
         Cutoffs cut;
         cut.n = nN;
         for (int q = 0; q < nN; ++q) cut.N[q] = Ns[q];
-        e = launch_cov_small(prec, G, D, coef, ldc, Nmax, cut, basis, cov, st);
+        e = launch_cov_small(prec, G, D, coef, ldc, Nmax, cut, basis, cov, st, corr);
+        return e;   // the correlations come from the same launch
     } else {
         for (int q = 0; q < nN && e == hipSuccess; ++q) {
             char* cq = (char*)cov + (size_t)q * G * D * D * es;

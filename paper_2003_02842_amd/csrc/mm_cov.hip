@@ -9,7 +9,8 @@
 //   k_cov_small     small D, any number of cutoffs: one workgroup per group of
 //                   series, a power of two of lanes per (i, j) pair, FP64 running sums
 //                   S0(N) = sum m_k P_k and S1(N) = sum m_k k P_k over k, read off
-//                   at every cutoff (Dirichlet S0/(2N+1), Fejer (S0 - S1/N)/(N+1))
+//                   at every cutoff (Dirichlet S0/(2N+1), Fejer (S0 - S1/N)/(N+1)),
+//                   and the correlations of each cutoff in the same launch
 //   k_split_bf16    X in BF16 hi/lo parts: hi = rne(x), lo = rne(x - hi)
 //   k_syrk_mfma256  lower-triangle 256x256 tiles of X X^T on v_mfma_f32_32x32x16_bf16,
 //                   hi*hi + hi*lo + lo*hi with FP32 accumulation, split over k; operand
@@ -66,13 +67,16 @@ struct SortedCutoffs {
 // into the running S0 = sum m_k P_k and S1 = sum m_k k P_k (m_0 = 1, m_k = 2,
 // P_k = Re c_k^(i) conj c_k^(j)), so every cutoff N reads
 //   Dirichlet (2pi)^2 S0/(2N+1),  Fejer (2pi)^2 (S0 - S1/N)/(N+1).
+// With corr, the correlation of every cutoff (as k_corr computes it, from the
+// stored covariances) is written too: the diagonal goes through LDS.
 template <typename CT, typename OT>
 __global__ void k_cov_small(int D, const CT* __restrict__ coef, int64_t ldc, int Nmax, SortedCutoffs cut, int basis,
-                            int G, int kl_bits, OT* __restrict__ cov)
+                            int G, int kl_bits, OT* __restrict__ cov, OT* __restrict__ corr)
 {
     constexpr int KC = 64;
     extern __shared__ __align__(16) char smem_raw[];
     double2* sh = reinterpret_cast<double2*>(smem_raw);   // D x KC
+    OT* dg = reinterpret_cast<OT*>(sh + D * KC);           // D: the diagonal at the current cutoff
     const int g = blockIdx.x;
     const int KL = 1 << kl_bits;
     const int npairs = D * (D + 1) / 2;
@@ -139,13 +143,27 @@ __global__ void k_cov_small(int D, const CT* __restrict__ coef, int64_t ldc, int
                 a0 = a1 = 0.0;
                 const int kcut = k0 + kend - 1;
                 while (q < cut.n && cut.N[q] == kcut) {
+                    OT vo = (OT)0;
+                    const int64_t mo = ((int64_t)cut.slot[q] * G + g) * D * D;
                     if (valid && lane == 0) {
                         const double Nd = (double)kcut;
                         double v = (basis == MM_DIRICHLET) ? S0 / (2.0 * Nd + 1.0) : (S0 - S1 / Nd) / (Nd + 1.0);
                         v *= fourpi2;
-                        OT* C = cov + ((int64_t)cut.slot[q] * G + g) * D * D;
-                        C[pi * D + pj] = (OT)v;
-                        C[pj * D + pi] = (OT)v;
+                        vo = (OT)v;
+                        OT* C = cov + mo;
+                        C[pi * D + pj] = vo;
+                        C[pj * D + pi] = vo;
+                        if (corr && pi == pj) dg[pi] = vo;
+                    }
+                    if (corr) {   // uniform: every thread reaches both barriers
+                        __syncthreads();
+                        if (valid && lane == 0) {
+                            const OT a = dg[pi], b = dg[pj];
+                            const OT r = (a > (OT)0 && b > (OT)0) ? vo / (sqrt(a) * sqrt(b)) : (OT)NAN;
+                            corr[mo + pi * D + pj] = r;
+                            corr[mo + pj * D + pi] = r;
+                        }
+                        __syncthreads();
                     }
                     ++q;
                 }
@@ -819,7 +837,7 @@ static SortedCutoffs sort_cutoffs(const Cutoffs& c)
 }
 
 hipError_t launch_cov_small(int prec, int32_t G, int32_t D, const void* coef, int64_t ldc, int32_t Nmax,
-                            const Cutoffs& cut, int basis, void* cov, hipStream_t st)
+                            const Cutoffs& cut, int basis, void* cov, hipStream_t st, void* corr)
 {
     SortedCutoffs sc = sort_cutoffs(cut);
     const int npairs = D * (D + 1) / 2;
@@ -828,14 +846,14 @@ hipError_t launch_cov_small(int prec, int32_t G, int32_t D, const void* coef, in
     while (kl_bits < 6 && npairs * (2 << kl_bits) <= 512) ++kl_bits;
     const int threads = std::max(64, ((npairs << kl_bits) + 63) / 64 * 64);
     if (D * 64 > 5 * threads) return hipErrorInvalidValue;   // k_cov_small stages at most 5 values per thread
-    const size_t lds = (size_t)D * 64 * sizeof(double2);
+    const size_t lds = (size_t)D * 64 * sizeof(double2) + (size_t)D * sizeof(double);
     prof_begin("k_cov_small", st);
     if (prec == MM_MIXED)
         hipLaunchKernelGGL((k_cov_small<float2, float>), dim3(G), dim3(threads), lds, st, D, (const float2*)coef, ldc,
-                           Nmax, sc, basis, G, kl_bits, (float*)cov);
+                           Nmax, sc, basis, G, kl_bits, (float*)cov, (float*)corr);
     else
         hipLaunchKernelGGL((k_cov_small<double2, double>), dim3(G), dim3(threads), lds, st, D, (const double2*)coef,
-                           ldc, Nmax, sc, basis, G, kl_bits, (double*)cov);
+                           ldc, Nmax, sc, basis, G, kl_bits, (double*)cov, (double*)corr);
     prof_end("k_cov_small", st);
     return hipGetLastError();
 }

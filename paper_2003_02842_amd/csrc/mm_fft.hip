@@ -196,30 +196,11 @@ __global__ __launch_bounds__(512) void k_fft_rows_ab(const T* __restrict__ grid,
     }
 }
 
-// FP64 tables of the two passes: W_L1^j, W_L2^j, the split W_L and W_Mr tables.
+// FP64 tables of the two passes (fft_tables_at), one entry per thread.
 template <typename T>
-__global__ void k_fft_tables(int L1, int L2, int L, int Mr, int lo_bits, int n_hi_L, int n_hi_M,
-                             typename CTf<T>::type* tw1, typename CTf<T>::type* tw2,
-                             typename CTf<T>::type* Llo, typename CTf<T>::type* Lhi,
-                             typename CTf<T>::type* Mlo, typename CTf<T>::type* Mhi)
+__global__ void k_fft_tables(FftTables<T> b)
 {
-    using C = typename CTf<T>::type;
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    auto tw = [](int64_t j, int64_t n) {
-        double s, c;
-        sincospi(2.0 * (double)(j % n) / (double)n, &s, &c);
-        return C{(T)c, (T)-s};
-    };
-    const int LO = 1 << lo_bits;
-    if (i < L1) { tw1[i] = tw(i, L1); return; }
-    i -= L1;
-    if (i < L2) { tw2[i] = tw(i, L2); return; }
-    i -= L2;
-    if (i < LO) { Llo[i] = tw(i, L); Mlo[i] = tw(i, Mr); return; }
-    i -= LO;
-    if (i < n_hi_L) { Lhi[i] = tw(i * LO, L); return; }
-    i -= n_hi_L;
-    if (i < n_hi_M) { Mhi[i] = tw(i * LO, Mr); return; }
+    fft_tables_at<T>(b, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // ---------------------------------------------------------------- host side
@@ -259,18 +240,11 @@ hipError_t launch_fft_ab(const Plan& p, const NufftWs& w, char* ws, int32_t s_be
 
 hipError_t launch_fft_ab_tables(const Plan& p, const NufftWs& w, char* ws, hipStream_t st)
 {
-    const int64_t total = (int64_t)p.L1 + p.L2 + (1 << p.tw_lo_bits) + p.tw_hi_L + p.tw_hi_M;
-    const int blocks = (int)((total + 255) / 256);
+    const int blocks = (int)((fft_tables_count(p) + 255) / 256);
     if (p.prec == MM_MIXED)
-        hipLaunchKernelGGL(k_fft_tables<float>, dim3(blocks), dim3(256), 0, st, p.L1, p.L2, p.L, p.Mr,
-                           p.tw_lo_bits, p.tw_hi_L, p.tw_hi_M, (float2*)(ws + w.tw1), (float2*)(ws + w.tw2),
-                           (float2*)(ws + w.tLlo), (float2*)(ws + w.tLhi), (float2*)(ws + w.tMlo),
-                           (float2*)(ws + w.tMhi));
+        hipLaunchKernelGGL(k_fft_tables<float>, dim3(blocks), dim3(256), 0, st, fft_tables_of<float>(p, w, ws));
     else
-        hipLaunchKernelGGL(k_fft_tables<double>, dim3(blocks), dim3(256), 0, st, p.L1, p.L2, p.L, p.Mr,
-                           p.tw_lo_bits, p.tw_hi_L, p.tw_hi_M, (double2*)(ws + w.tw1), (double2*)(ws + w.tw2),
-                           (double2*)(ws + w.tLlo), (double2*)(ws + w.tLhi), (double2*)(ws + w.tMlo),
-                           (double2*)(ws + w.tMhi));
+        hipLaunchKernelGGL(k_fft_tables<double>, dim3(blocks), dim3(256), 0, st, fft_tables_of<double>(p, w, ws));
     return hipGetLastError();
 }
 

@@ -15,11 +15,53 @@
 
 #include <stdint.h>
 
+#include "mm_internal.h"
+
 namespace mm {
 
 template <typename T> struct CTf;
 template <> struct CTf<float> { using type = float2; };
 template <> struct CTf<double> { using type = double2; };
+
+// Twiddle tables of the two-pass FFT (FP64 sincospi, rounded to T): W_L1^j,
+// W_L2^j, and the split tables W_L^m, W_Mr^m = lo[m mod 2^lo_bits] hi[m >> lo_bits].
+template <typename T>
+struct FftTables {
+    int L1, L2, L, Mr, lo_bits, n_hi_L, n_hi_M;
+    typename CTf<T>::type *tw1, *tw2, *Llo, *Lhi, *Mlo, *Mhi;
+};
+template <typename T>
+inline FftTables<T> fft_tables_of(const Plan& p, const NufftWs& w, char* ws)
+{
+    using C = typename CTf<T>::type;
+    return FftTables<T>{p.L1, p.L2, p.L, p.Mr, p.tw_lo_bits, p.tw_hi_L, p.tw_hi_M, (C*)(ws + w.tw1), (C*)(ws + w.tw2),
+                        (C*)(ws + w.tLlo), (C*)(ws + w.tLhi), (C*)(ws + w.tMlo), (C*)(ws + w.tMhi)};
+}
+// entries in order: L1, L2, 2^lo_bits (both lo tables), n_hi_L, n_hi_M
+inline int64_t fft_tables_count(const Plan& p)
+{
+    return (int64_t)p.L1 + p.L2 + (1 << p.tw_lo_bits) + p.tw_hi_L + p.tw_hi_M;
+}
+template <typename T>
+__device__ __forceinline__ void fft_tables_at(const FftTables<T>& b, int64_t i)
+{
+    using C = typename CTf<T>::type;
+    auto tw = [](int64_t j, int64_t n) {
+        double s, c;
+        sincospi(2.0 * (double)(j % n) / (double)n, &s, &c);
+        return C{(T)c, (T)-s};
+    };
+    const int LO = 1 << b.lo_bits;
+    if (i < b.L1) { b.tw1[i] = tw(i, b.L1); return; }
+    i -= b.L1;
+    if (i < b.L2) { b.tw2[i] = tw(i, b.L2); return; }
+    i -= b.L2;
+    if (i < LO) { b.Llo[i] = tw(i, b.L); b.Mlo[i] = tw(i, b.Mr); return; }
+    i -= LO;
+    if (i < b.n_hi_L) { b.Lhi[i] = tw(i * LO, b.L); return; }
+    i -= b.n_hi_L;
+    if (i < b.n_hi_M) { b.Mhi[i] = tw(i * LO, b.Mr); return; }
+}
 
 // ---------------------------------------------------------------- compile-time twiddles
 // cos and sin of 2 pi m / n by octant reduction and Taylor series (|x| <= pi/4).

@@ -167,15 +167,12 @@ static void fused_w(const Plan& p, const NufftWs& w, char* ws, int32_t S, const 
                        (const float*)(ws + w.dfac), p.N, coef, ldc);
 }
 
-hipError_t launch_nufft_fused(const Plan& p, const NufftWs& w, char* ws, int32_t S, const int64_t* offsets,
-                              const double* t, const void* dp, int dp_fp64, double t0, double T, void* coef,
-                              int64_t ldc, hipStream_t st)
+hipError_t launch_nufft_fused(const Plan& p, const NufftWs& w, char* ws, int32_t S, const double* t, const void* dp,
+                              int dp_fp64, double t0, double T, void* coef, int64_t ldc, hipStream_t st)
 {
     if (S <= 0) return hipSuccess;
     const double scale = (double)p.Mr / (T - t0);
-    int64_t* ranges = (int64_t*)(ws + w.ranges);
-    hipError_t e = launch_tile_ranges(p, offsets, t, 0, S, 1, kFusedMaxCells, t0, T, ranges, st);
-    if (e != hipSuccess) return e;
+    const int64_t* ranges = (const int64_t*)(ws + w.ranges);
     const DpAny src{dp, dp_fp64};
     prof_begin("k_nufft_fused", st);
     switch (p.kp.w) {

@@ -136,7 +136,19 @@ struct NufftWs {
 NufftWs nufft_workspace(const Plan& p, int32_t S);
 
 // Launchers (mm_nufft.hip).  All asynchronous on `st`.
-hipError_t launch_prep(const Plan& p, const NufftWs& w, char* ws, hipStream_t st);
+// Tile event ranges for the set-up launch to compute as well: the series
+// [s_begin, s_begin + s_count) over tiles of tc cells, into `ranges`.
+struct RangeReq {
+    const int64_t* offsets;
+    const double* t;
+    int32_t s_begin, s_count;
+    int tiles, tc;
+    double t0, T;
+    int64_t* ranges;
+};
+// Deconvolution factors and FFT tables (one launch with the two-pass FFT, which
+// also takes the tile ranges of rr), before the spreading.
+hipError_t launch_prep(const Plan& p, const NufftWs& w, char* ws, hipStream_t st, const RangeReq* rr = nullptr);
 hipError_t launch_validate(int32_t S, const int64_t* offsets, const double* t, const void* dp, int dp_fp64,
                            double t0, double T, int* flag, hipStream_t st);
 // Destination of the split fused into the FFT's row pass: X = s_k c_k written as
@@ -153,15 +165,14 @@ struct SplitOut {
 hipError_t launch_nufft_tiled(const Plan& p, const NufftWs& w, char* ws, int32_t s_begin, int32_t s_count,
                               const int64_t* offsets, const double* t, const void* dp, int dp_fp64,
                               double t0, double T, void* coef, int64_t ldc, hipStream_t st,
-                              const SplitOut* so = nullptr);
+                              const SplitOut* so = nullptr, bool ranges_ready = false);
 hipError_t launch_spread_poly(const Plan& p, int s_count, const double* t, const void* dp, int dp_fp64, double t0,
                               double t_end, const int64_t* ranges, int tiles, float* grid, int64_t grid_stride,
                               hipStream_t st);
-// Fused small-grid NUFFT (mm_fused.hip): the tile search over one whole-grid tile,
-// then one workgroup per series from events to coefficients.
-hipError_t launch_nufft_fused(const Plan& p, const NufftWs& w, char* ws, int32_t S, const int64_t* offsets,
-                              const double* t, const void* dp, int dp_fp64, double t0, double T,
-                              void* coef, int64_t ldc, hipStream_t st);
+// Fused small-grid NUFFT (mm_fused.hip): one workgroup per series from events to
+// coefficients, on the ranges of one whole-grid tile per series (launch_prep).
+hipError_t launch_nufft_fused(const Plan& p, const NufftWs& w, char* ws, int32_t S, const double* t, const void* dp,
+                              int dp_fp64, double t0, double T, void* coef, int64_t ldc, hipStream_t st);
 // Event ranges of every (series, tile of tc cells) (k_tile_ranges).
 hipError_t launch_tile_ranges(const Plan& p, const int64_t* offsets, const double* t, int32_t s_begin,
                               int32_t s_count, int tiles, int tc, double t0, double T, int64_t* ranges,
@@ -200,8 +211,9 @@ struct Cutoffs {
     int n;
     int N[kMaxCutoffs];
 };
+// (with corr, the correlations too, in the same launch)
 hipError_t launch_cov_small(int prec, int32_t G, int32_t D, const void* coef, int64_t ldc, int32_t Nmax,
-                            const Cutoffs& cut, int basis, void* cov, hipStream_t st);
+                            const Cutoffs& cut, int basis, void* cov, hipStream_t st, void* corr = nullptr);
 hipError_t launch_corr(int prec, int64_t mats, int32_t D, const void* cov, void* corr, hipStream_t st);
 size_t cov_mfma_workspace(int32_t G, int32_t D, int32_t Nmax, SyrkChoice sc = {});
 hipError_t launch_pairwise_select(int prec, int32_t G, int32_t D, const int32_t* qidx, const void* sweep, void* cov,

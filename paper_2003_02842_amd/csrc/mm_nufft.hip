@@ -4,6 +4,8 @@
 //                  kernel, one wave per k
 //   k_tile_ranges  per (series, grid tile) event ranges by binary search on the
 //                  sorted event keys
+//   k_setup        with the two-pass FFT: the deconvolution factors, its twiddle
+//                  tables and the tile ranges in one launch
 //   k_spread       spreading onto the periodic oversampled grid (Eq. Der:15), one
 //                  workgroup per (series, grid tile), each cell gathering its
 //                  events from LDS and evaluating the kernel formula per pair; no
@@ -25,6 +27,7 @@
 // output sits in digit-reversed positions.
 #include <hip/hip_runtime.h>
 
+#include "mm_fft_codelets.h"
 #include "mm_internal.h"
 #include "mm_spread.h"
 
@@ -293,13 +296,21 @@ __device__ __forceinline__ T kern_eval(T x, const KEval<T>& k)
 // [l0, l0 + w) meet cells [a, a + len) + m Mr, i.e. keys l0 in
 // [a + m Mr - w + 1, a + len + m Mr); entry 2(m+1) is the first such event and
 // 2(m+1)+1 one past the last (lower bounds on the sorted keys).
+struct RangeJob {
+    const int64_t* offsets;
+    const double* t;
+    int s_begin, s_count, tiles, tc, Mr, w;
+    double hw, t0, span, scale;
+    int64_t* ranges;
+};
+
 template <bool EXACT_DIV>
-__global__ void k_tile_ranges(const int64_t* __restrict__ offsets, const double* __restrict__ t, int s_begin,
-                              int s_count, int tiles, int tc, int Mr, int w, double hw, double t0, double span,
-                              double scale, int64_t* __restrict__ ranges)
+__device__ __forceinline__ void tile_range_at(const RangeJob& j, int64_t idx)
 {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)s_count * tiles * 6) return;
+    const int64_t* __restrict__ offsets = j.offsets;
+    const double* __restrict__ t = j.t;
+    const int s_begin = j.s_begin, tiles = j.tiles, tc = j.tc, Mr = j.Mr, w = j.w;
+    const double hw = j.hw, t0 = j.t0, span = j.span, scale = j.scale;
     const int q = (int)(idx % 6);
     const int64_t rest = idx / 6;
     const int tile = (int)(rest % tiles);
@@ -317,7 +328,15 @@ __global__ void k_tile_ranges(const int64_t* __restrict__ offsets, const double*
         if (l0 < key) lo = mid + 1;
         else hi = mid;
     }
-    ranges[idx] = lo;
+    j.ranges[idx] = lo;
+}
+
+template <bool EXACT_DIV>
+__global__ void k_tile_ranges(RangeJob j)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)j.s_count * j.tiles * 6) return;
+    tile_range_at<EXACT_DIV>(j, idx);
 }
 
 // One staged event.  key = first-tap cell relative to the tile plus w - 1 (a
@@ -976,11 +995,10 @@ __global__ void k_prep(int L1, int L2, int L, int Mr, FFTDesc F1, FFTDesc F2, ty
 // nodes, one node per lane, added up by lane shuffles; the Gaussian and KB
 // transforms have closed forms (lane 0).
 template <typename T>
-__global__ __launch_bounds__(64) void k_deconv(int N, int Mr, KernParams kp, GLRule gl, T* __restrict__ dfac)
+__device__ __forceinline__ void deconv_wave(int k, int q, int N, int Mr, const KernParams& kp, const GLRule& gl,
+                                            T* __restrict__ dfac)
 {
-    const int k = blockIdx.x;
     if (k > N) return;
-    const int q = threadIdx.x;
     const double pi = 3.14159265358979323846;
     if (kp.kind == MM_ES) {
         const double nu = (double)k / (double)Mr;
@@ -994,6 +1012,31 @@ __global__ __launch_bounds__(64) void k_deconv(int N, int Mr, KernParams kp, GLR
         if (q == 0) dfac[k] = (T)(1.0 / (2.0 * pi * (2.0 * kp.hw * acc)));
     } else if (q == 0) {
         dfac[k] = (T)deconv_factor(kp, k, Mr, gl);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_deconv(int N, int Mr, KernParams kp, GLRule gl, T* __restrict__ dfac)
+{
+    deconv_wave<T>(blockIdx.x, threadIdx.x, N, Mr, kp, gl, dfac);
+}
+
+// The set-up of a two-pass-FFT plan in one launch of 256-thread blocks: blocks
+// [0, nb_dec) the deconvolution factors (one wave per k, as k_deconv), the next
+// nb_tab blocks the FFT's twiddle tables (as k_fft_tables), the rest the tile
+// event ranges of rj (as k_tile_ranges; none if rj.s_count is 0).
+template <typename T, bool EXACT_DIV>
+__global__ __launch_bounds__(256) void k_setup(int N, int Mr, KernParams kp, GLRule gl, T* __restrict__ dfac,
+                                               int nb_dec, FftTables<T> tb, int nb_tab, RangeJob rj)
+{
+    const int b = blockIdx.x;
+    if (b < nb_dec) {
+        deconv_wave<T>(4 * b + ((int)threadIdx.x >> 6), (int)threadIdx.x & 63, N, Mr, kp, gl, dfac);
+    } else if (b < nb_dec + nb_tab) {
+        fft_tables_at<T>(tb, (int64_t)(b - nb_dec) * 256 + threadIdx.x);
+    } else {
+        const int64_t idx = (int64_t)(b - nb_dec - nb_tab) * 256 + threadIdx.x;
+        if (idx < (int64_t)rj.s_count * rj.tiles * 6) tile_range_at<EXACT_DIV>(rj, idx);
     }
 }
 
@@ -1029,24 +1072,53 @@ static GLRule host_gl()
     return rule.g;
 }
 
-hipError_t launch_prep(const Plan& p, const NufftWs& w, char* ws, hipStream_t st)
+template <typename T>
+static void setup_t(const Plan& p, const NufftWs& w, char* ws, const GLRule& gl, const RangeJob& rj,
+                    int64_t n_ranges, hipStream_t st)
+{
+    const int nb_dec = (p.N + 1 + 3) / 4;
+    const int nb_tab = (int)((fft_tables_count(p) + 255) / 256);
+    const int nb_rng = (int)((n_ranges + 255) / 256);
+    if (p.prec == MM_PLAIN_FP64)
+        hipLaunchKernelGGL((k_setup<T, true>), dim3(nb_dec + nb_tab + nb_rng), dim3(256), 0, st, p.N, p.Mr, p.kp, gl,
+                           (T*)(ws + w.dfac), nb_dec, fft_tables_of<T>(p, w, ws), nb_tab, rj);
+    else
+        hipLaunchKernelGGL((k_setup<T, false>), dim3(nb_dec + nb_tab + nb_rng), dim3(256), 0, st, p.N, p.Mr, p.kp, gl,
+                           (T*)(ws + w.dfac), nb_dec, fft_tables_of<T>(p, w, ws), nb_tab, rj);
+}
+
+hipError_t launch_prep(const Plan& p, const NufftWs& w, char* ws, hipStream_t st, const RangeReq* rr)
 {
     GLRule gl = host_gl();
-    // the generic FFT passes' tables (the two-pass form has its own, k_fft_tables)
-    if (!p.fft_ab) {
-        const int64_t total = 2ll * p.L1 + 2ll * p.L2 + 2ll * p.L;
-        const int blocks = (int)((total + 255) / 256);
-        prof_begin("k_prep", st);
-        if (p.prec == MM_MIXED)
-            hipLaunchKernelGGL(k_prep<float>, dim3(blocks), dim3(256), 0, st, p.L1, p.L2, p.L, p.Mr, p.F1, p.F2,
-                               (float2*)(ws + w.tw1), (float2*)(ws + w.tw2), (float2*)(ws + w.twL),
-                               (float2*)(ws + w.twM), (int*)(ws + w.rev1), (int*)(ws + w.pos2));
-        else
-            hipLaunchKernelGGL(k_prep<double>, dim3(blocks), dim3(256), 0, st, p.L1, p.L2, p.L, p.Mr, p.F1, p.F2,
-                               (double2*)(ws + w.tw1), (double2*)(ws + w.tw2), (double2*)(ws + w.twL),
-                               (double2*)(ws + w.twM), (int*)(ws + w.rev1), (int*)(ws + w.pos2));
-        prof_end("k_prep", st);
+    if (p.fft_ab) {
+        // deconvolution factors, twiddle tables and (if asked) tile ranges: one launch
+        RangeJob rj{};
+        int64_t nr = 0;
+        if (rr && rr->s_count > 0) {
+            const double span = rr->T - rr->t0;
+            rj = RangeJob{rr->offsets, rr->t, rr->s_begin, rr->s_count, rr->tiles, rr->tc, p.Mr, p.kp.w, p.kp.hw,
+                          rr->t0, span, (double)p.Mr / span, rr->ranges};
+            nr = (int64_t)rr->s_count * rr->tiles * 6;
+        }
+        prof_begin("k_setup", st);
+        if (p.prec == MM_MIXED) setup_t<float>(p, w, ws, gl, rj, nr, st);
+        else setup_t<double>(p, w, ws, gl, rj, nr, st);
+        prof_end("k_setup", st);
+        return hipGetLastError();
     }
+    // the generic FFT passes' tables
+    const int64_t total = 2ll * p.L1 + 2ll * p.L2 + 2ll * p.L;
+    const int blocks = (int)((total + 255) / 256);
+    prof_begin("k_prep", st);
+    if (p.prec == MM_MIXED)
+        hipLaunchKernelGGL(k_prep<float>, dim3(blocks), dim3(256), 0, st, p.L1, p.L2, p.L, p.Mr, p.F1, p.F2,
+                           (float2*)(ws + w.tw1), (float2*)(ws + w.tw2), (float2*)(ws + w.twL),
+                           (float2*)(ws + w.twM), (int*)(ws + w.rev1), (int*)(ws + w.pos2));
+    else
+        hipLaunchKernelGGL(k_prep<double>, dim3(blocks), dim3(256), 0, st, p.L1, p.L2, p.L, p.Mr, p.F1, p.F2,
+                           (double2*)(ws + w.tw1), (double2*)(ws + w.tw2), (double2*)(ws + w.twL),
+                           (double2*)(ws + w.twM), (int*)(ws + w.rev1), (int*)(ws + w.pos2));
+    prof_end("k_prep", st);
     prof_begin("k_deconv", st);
     if (p.prec == MM_MIXED)
         hipLaunchKernelGGL(k_deconv<float>, dim3(p.N + 1), dim3(64), 0, st, p.N, p.Mr, p.kp, gl,
@@ -1056,7 +1128,9 @@ hipError_t launch_prep(const Plan& p, const NufftWs& w, char* ws, hipStream_t st
                            (double*)(ws + w.dfac));
     prof_end("k_deconv", st);
     hipError_t e = hipGetLastError();
-    if (e == hipSuccess && p.fft_ab) e = launch_fft_ab_tables(p, w, ws, st);
+    if (e == hipSuccess && rr)
+        e = launch_tile_ranges(p, rr->offsets, rr->t, rr->s_begin, rr->s_count, rr->tiles, rr->tc, rr->t0, rr->T,
+                               rr->ranges, st);
     return e;
 }
 
@@ -1111,13 +1185,13 @@ hipError_t launch_tile_ranges(const Plan& p, const int64_t* offsets, const doubl
     const double span = T - t0;
     const int64_t nr = (int64_t)s_count * tiles * 6;
     if (nr == 0) return hipSuccess;
+    const RangeJob j{offsets, t, s_begin, s_count, tiles, tc, p.Mr, p.kp.w, p.kp.hw, t0, span, (double)p.Mr / span,
+                     ranges};
     prof_begin("k_tile_ranges", st);
     if (p.prec == MM_PLAIN_FP64)
-        hipLaunchKernelGGL(k_tile_ranges<true>, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, st, offsets, t,
-                           s_begin, s_count, tiles, tc, p.Mr, p.kp.w, p.kp.hw, t0, span, (double)p.Mr / span, ranges);
+        hipLaunchKernelGGL(k_tile_ranges<true>, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, st, j);
     else
-        hipLaunchKernelGGL(k_tile_ranges<false>, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, st, offsets, t,
-                           s_begin, s_count, tiles, tc, p.Mr, p.kp.w, p.kp.hw, t0, span, (double)p.Mr / span, ranges);
+        hipLaunchKernelGGL(k_tile_ranges<false>, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, st, j);
     prof_end("k_tile_ranges", st);
     return hipGetLastError();
 }
@@ -1125,15 +1199,18 @@ hipError_t launch_tile_ranges(const Plan& p, const int64_t* offsets, const doubl
 template <typename T>
 static hipError_t nufft_tiled_t(const Plan& p, const NufftWs& w, char* ws, int32_t s_begin, int32_t s_count,
                                 const int64_t* offsets, const double* t, const void* dp, int dp_fp64, double t0,
-                                double T_, void* coef, int64_t ldc, hipStream_t st, const SplitOut* so)
+                                double T_, void* coef, int64_t ldc, hipStream_t st, const SplitOut* so,
+                                bool ranges_ready)
 {
     using C = typename CT<T>::type;
     T* grid = (T*)(ws + w.grid);
     const int64_t gstride = 2ll * p.L1 * p.L2p;
     const int tiles = (p.Mr + p.tile - 1) / p.tile;
     int64_t* ranges = (int64_t*)(ws + w.ranges);
-    hipError_t er = launch_tile_ranges(p, offsets, t, s_begin, s_count, tiles, p.tile, t0, T_, ranges, st);
-    if (er != hipSuccess) return er;
+    if (!ranges_ready) {
+        hipError_t er = launch_tile_ranges(p, offsets, t, s_begin, s_count, tiles, p.tile, t0, T_, ranges, st);
+        if (er != hipSuccess) return er;
+    }
     // recorded under the name of the kernel that runs
     const char* spread_name = (sizeof(T) == 4 && p.poly) ? "k_spread_poly" : "k_spread";
     prof_begin(spread_name, st);
@@ -1177,13 +1254,15 @@ static hipError_t nufft_tiled_t(const Plan& p, const NufftWs& w, char* ws, int32
 
 hipError_t launch_nufft_tiled(const Plan& p, const NufftWs& w, char* ws, int32_t s_begin, int32_t s_count,
                               const int64_t* offsets, const double* t, const void* dp, int dp_fp64, double t0,
-                              double T, void* coef, int64_t ldc, hipStream_t st, const SplitOut* so)
+                              double T, void* coef, int64_t ldc, hipStream_t st, const SplitOut* so, bool ranges_ready)
 {
     if (s_count <= 0) return hipSuccess;
     if (p.prec == MM_MIXED)
-        return nufft_tiled_t<float>(p, w, ws, s_begin, s_count, offsets, t, dp, dp_fp64, t0, T, coef, ldc, st, so);
+        return nufft_tiled_t<float>(p, w, ws, s_begin, s_count, offsets, t, dp, dp_fp64, t0, T, coef, ldc, st, so,
+                                    ranges_ready);
     if (so) return hipErrorInvalidValue;
-    return nufft_tiled_t<double>(p, w, ws, s_begin, s_count, offsets, t, dp, dp_fp64, t0, T, coef, ldc, st, nullptr);
+    return nufft_tiled_t<double>(p, w, ws, s_begin, s_count, offsets, t, dp, dp_fp64, t0, T, coef, ldc, st, nullptr,
+                                 ranges_ready);
 }
 
 
