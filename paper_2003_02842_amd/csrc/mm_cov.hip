@@ -68,7 +68,8 @@ struct SortedCutoffs {
 // P_k = Re c_k^(i) conj c_k^(j)), so every cutoff N reads
 //   Dirichlet (2pi)^2 S0/(2N+1),  Fejer (2pi)^2 (S0 - S1/N)/(N+1).
 // With corr, the correlation of every cutoff (as k_corr computes it, from the
-// stored covariances) is written too: the diagonal goes through LDS.
+// stored covariances) is written too, after the last k, from copies of every
+// cutoff's covariances kept in LDS; the KL lanes of a pair share the cutoffs.
 template <typename CT, typename OT>
 __global__ void k_cov_small(int D, const CT* __restrict__ coef, int64_t ldc, int Nmax, SortedCutoffs cut, int basis,
                             int G, int kl_bits, OT* __restrict__ cov, OT* __restrict__ corr)
@@ -76,7 +77,8 @@ __global__ void k_cov_small(int D, const CT* __restrict__ coef, int64_t ldc, int
     constexpr int KC = 64;
     extern __shared__ __align__(16) char smem_raw[];
     double2* sh = reinterpret_cast<double2*>(smem_raw);   // D x KC
-    OT* dg = reinterpret_cast<OT*>(sh + D * KC);           // D: the diagonal at the current cutoff
+    OT* dg = reinterpret_cast<OT*>(sh + D * KC);           // n x D: the diagonal at each cutoff (with corr)
+    OT* vals = dg + cut.n * D;                             // n x npairs: every pair at each cutoff
     const int g = blockIdx.x;
     const int KL = 1 << kl_bits;
     const int npairs = D * (D + 1) / 2;
@@ -143,32 +145,32 @@ __global__ void k_cov_small(int D, const CT* __restrict__ coef, int64_t ldc, int
                 a0 = a1 = 0.0;
                 const int kcut = k0 + kend - 1;
                 while (q < cut.n && cut.N[q] == kcut) {
-                    OT vo = (OT)0;
-                    const int64_t mo = ((int64_t)cut.slot[q] * G + g) * D * D;
                     if (valid && lane == 0) {
                         const double Nd = (double)kcut;
                         double v = (basis == MM_DIRICHLET) ? S0 / (2.0 * Nd + 1.0) : (S0 - S1 / Nd) / (Nd + 1.0);
                         v *= fourpi2;
-                        vo = (OT)v;
-                        OT* C = cov + mo;
-                        C[pi * D + pj] = vo;
-                        C[pj * D + pi] = vo;
-                        if (corr && pi == pj) dg[pi] = vo;
-                    }
-                    if (corr) {   // uniform: every thread reaches both barriers
-                        __syncthreads();
-                        if (valid && lane == 0) {
-                            const OT a = dg[pi], b = dg[pj];
-                            const OT r = (a > (OT)0 && b > (OT)0) ? vo / (sqrt(a) * sqrt(b)) : (OT)NAN;
-                            corr[mo + pi * D + pj] = r;
-                            corr[mo + pj * D + pi] = r;
+                        OT* C = cov + ((int64_t)cut.slot[q] * G + g) * D * D;
+                        C[pi * D + pj] = (OT)v;
+                        C[pj * D + pi] = (OT)v;
+                        if (corr) {
+                            vals[q * npairs + pidx] = (OT)v;
+                            if (pi == pj) dg[q * D + pi] = (OT)v;
                         }
-                        __syncthreads();
                     }
                     ++q;
                 }
             }
         }
+    }
+    if (!corr) return;
+    __syncthreads();
+    if (!valid) return;
+    for (q = lane; q < cut.n; q += KL) {
+        const int64_t mo = ((int64_t)cut.slot[q] * G + g) * D * D;
+        const OT c = vals[q * npairs + pidx], a = dg[q * D + pi], b = dg[q * D + pj];
+        const OT r = (a > (OT)0 && b > (OT)0) ? c / (sqrt(a) * sqrt(b)) : (OT)NAN;
+        corr[mo + pi * D + pj] = r;
+        corr[mo + pj * D + pi] = r;
     }
 }
 
@@ -846,16 +848,23 @@ hipError_t launch_cov_small(int prec, int32_t G, int32_t D, const void* coef, in
     while (kl_bits < 6 && npairs * (2 << kl_bits) <= 512) ++kl_bits;
     const int threads = std::max(64, ((npairs << kl_bits) + 63) / 64 * 64);
     if (D * 64 > 5 * threads) return hipErrorInvalidValue;   // k_cov_small stages at most 5 values per thread
-    const size_t lds = (size_t)D * 64 * sizeof(double2) + (size_t)D * sizeof(double);
+    // the correlations in the same launch while every cutoff's values fit in LDS
+    const size_t os = prec == MM_MIXED ? sizeof(float) : sizeof(double);
+    const size_t lds_corr = (size_t)sc.n * (D + npairs) * os;
+    const bool fold = corr && (size_t)D * 64 * sizeof(double2) + lds_corr <= 64 * 1024;
+    const size_t lds = (size_t)D * 64 * sizeof(double2) + (fold ? lds_corr : 0);
+    void* kc = fold ? corr : nullptr;
     prof_begin("k_cov_small", st);
     if (prec == MM_MIXED)
         hipLaunchKernelGGL((k_cov_small<float2, float>), dim3(G), dim3(threads), lds, st, D, (const float2*)coef, ldc,
-                           Nmax, sc, basis, G, kl_bits, (float*)cov, (float*)corr);
+                           Nmax, sc, basis, G, kl_bits, (float*)cov, (float*)kc);
     else
         hipLaunchKernelGGL((k_cov_small<double2, double>), dim3(G), dim3(threads), lds, st, D, (const double2*)coef,
-                           ldc, Nmax, sc, basis, G, kl_bits, (double*)cov, (double*)corr);
+                           ldc, Nmax, sc, basis, G, kl_bits, (double*)cov, (double*)kc);
     prof_end("k_cov_small", st);
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && corr && !fold) e = launch_corr(prec, (int64_t)cut.n * G, D, cov, corr, st);
+    return e;
 }
 
 hipError_t launch_corr(int prec, int64_t mats, int32_t D, const void* cov, void* corr, hipStream_t st)
