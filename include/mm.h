@@ -85,6 +85,10 @@ typedef struct {
                                   0: the built-in model (256 for large D and long k ranges) */
     int32_t syrk_splits;       /* ... and the number of k-ranges each tile's sum is split into (partial tiles
                                   summed afterwards), >= 1, at most one per 32 real columns; 0: the model */
+    double moment_density;     /* MM_MIXED spreading with per-tap polynomials: grid tiles holding at least this
+                                  many events per cell are spread from per-cell moments (sum_d c_jd M_l[d],
+                                  M_l[d] the sum of v s^d over the events starting at cell l), the others by
+                                  per-event taps; 0: the default (3.0), < 0: per-event taps everywhere */
 } mm_tuning;
 
 /* What the planner chose (host only, no device work). */

@@ -96,8 +96,8 @@ static hipError_t enqueue_nufft(const Plan& p, const NufftWs& w, char* wsb, int3
         const bool fz = use_fused(p, S);
         if (fz && so) return hipErrorInvalidValue;
         const bool one_pass = fz || S <= w.S_grid;
-        const RangeReq rr{offsets, t, 0, S, fz ? 1 : (p.Mr + p.tile - 1) / p.tile, fz ? kFusedMaxCells : p.tile, t0,
-                          T, (int64_t*)(wsb + w.ranges)};
+        const RangeReq rr{offsets, t, 0, S, fz ? 1 : (p.Mr + kRangeCells - 1) / kRangeCells,
+                          fz ? kFusedMaxCells : kRangeCells, t0, T, (int64_t*)(wsb + w.ranges)};
         hipError_t e = launch_prep(p, w, wsb, st, one_pass ? &rr : nullptr);
         if (e != hipSuccess) return e;
         if (fz) return launch_nufft_fused(p, w, wsb, S, t, dp, dp_is_fp64, t0, T, coef, ldc, st);
@@ -369,9 +369,10 @@ mm_status mm_estimate(int32_t G, int32_t D, const int64_t* offsets, const double
     put(key, basis); put(key, kernel); put(key, tol); put(key, prec); put(key, ldc); put(key, ws_bytes);
     put(key, coef_out);
     put(key, ptrs);
-    const mm_tuning tz = tune ? *tune : mm_tuning{0, 0.0, 0, 0, 0.0, 0, 0, 0, 0};
+    const mm_tuning tz = tune ? *tune : mm_tuning{0, 0.0, 0, 0, 0.0, 0, 0, 0, 0, 0.0};
     put(key, tz.width); put(key, tz.sigma); put(key, tz.tile); put(key, tz.fused); put(key, tz.es_beta_per_tap);
     put(key, tz.fft_generic); put(key, tz.spread_direct); put(key, tz.syrk_tile); put(key, tz.syrk_splits);
+    put(key, tz.moment_density);
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return MM_ERR_HIP;
     put(key, dev);

@@ -18,6 +18,8 @@ constexpr int kMaxCutoffs = 128;   // cutoffs per mm_cov call
 constexpr int kGLNodes = 64;       // positive nodes of the 128-point Gauss-Legendre rule
 constexpr int kFusedMaxCells = 8192;          // largest grid of the fused single-workgroup NUFFT
 constexpr size_t kFusedMaxLds = 80 * 1024;    // its LDS budget (two workgroups per CU)
+constexpr double kMomDensity = 3.0;         // events per cell from which a tile spreads from moments
+constexpr int kRangeCells = 1024;           // cells per event-range sub-tile (spreading tiles are 1-4 of them)
 constexpr int kFusedMinSeries = 64;           // series from which the planner's "auto" takes it
 
 // Exact unsigned division a / d for a < 2^22, d < 2^20: (a * M) >> 42, M = ceil(2^42/d).
@@ -106,6 +108,8 @@ struct Plan {
     double poly_err;     // largest deviation of the polynomials from the kernel (FP64 evaluation)
     PolyParams pp;
     int tile;            // cells per spreading tile: 1024, 2048 or 4096 (256 threads x 4, 8, 16 cells)
+    double mom_density;  // > 0: tiles with at least this many events per cell spread from per-cell
+                         // moments (k_spread_mom); 0: all by k_spread_poly
     int fused;           // 1: the fused single-workgroup NUFFT can run this plan (mm_fused.hip)
     int fused_min_series;   // ... and runs it for calls with at least this many series
 };
@@ -167,7 +171,7 @@ hipError_t launch_nufft_tiled(const Plan& p, const NufftWs& w, char* ws, int32_t
                               double t0, double T, void* coef, int64_t ldc, hipStream_t st,
                               const SplitOut* so = nullptr, bool ranges_ready = false);
 hipError_t launch_spread_poly(const Plan& p, int s_count, const double* t, const void* dp, int dp_fp64, double t0,
-                              double t_end, const int64_t* ranges, int tiles, float* grid, int64_t grid_stride,
+                              double t_end, const int64_t* ranges, int nsub, float* grid, int64_t grid_stride,
                               hipStream_t st);
 // Fused small-grid NUFFT (mm_fused.hip): one workgroup per series from events to
 // coefficients, on the ranges of one whole-grid tile per series (launch_prep).

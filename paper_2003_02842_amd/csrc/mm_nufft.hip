@@ -339,6 +339,22 @@ __global__ void k_tile_ranges(RangeJob j)
     tile_range_at<EXACT_DIV>(j, idx);
 }
 
+// The three event ranges (m = -1, 0, 1) of spreading tile x of series s from the
+// ranges of its sub-tiles of kRangeCells cells (nsub per series, rsub per tile):
+// events are sorted by key, so range m runs from its first sub-tile's start to
+// its last sub-tile's end.
+__device__ __forceinline__ void tile_event_ranges(const int64_t* __restrict__ ranges, int s, int x, int nsub, int rsub,
+                                                  int64_t (&rb)[3], int64_t (&re)[3])
+{
+    const int64_t* r0 = ranges + ((int64_t)s * nsub + (int64_t)x * rsub) * 6;
+    const int64_t* r1 = ranges + ((int64_t)s * nsub + min(x * rsub + rsub, nsub) - 1) * 6;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        rb[m] = r0[2 * m];
+        re[m] = r1[2 * m + 1];
+    }
+}
+
 // One staged event.  key = first-tap cell relative to the tile plus w - 1 (a
 // small integer held exactly as a float); the tap at cell c has index
 // j = c + w - 1 - key and kernel argument x = j + x0 with x0 = 1 - f - hw.
@@ -402,8 +418,8 @@ __device__ __forceinline__ T pair_value(T j, const EvRecK<T, KIND>& r, const KEv
 template <typename T, typename DPT, int KIND, int CPT>
 __global__ __launch_bounds__(256) void k_spread(const double* __restrict__ t, const DPT* __restrict__ dp,
                                                 double t0, double span, double scale, KernParams kp, int Mr,
-                                                const int64_t* __restrict__ ranges, int tiles, int L2, int L2p,
-                                                FastDiv divL2, T* __restrict__ grid, int64_t grid_stride)
+                                                const int64_t* __restrict__ ranges, int nsub, int rsub, int L2,
+                                                int L2p, FastDiv divL2, T* __restrict__ grid, int64_t grid_stride)
 {
     constexpr bool EXACT = sizeof(T) == 8;
     constexpr int TC = 256 * CPT;
@@ -415,14 +431,13 @@ __global__ __launch_bounds__(256) void k_spread(const double* __restrict__ t, co
     const int len = min(TC, Mr - a);
     const int w = kp.w;
     const KEval<T> ke(kp);
-    const int64_t* rg = ranges + ((int64_t)blockIdx.y * tiles + blockIdx.x) * 6;
     // The three key ranges (m = -1, 0, 1) as one list of chunks of EC events.
-    int64_t rb[3], nchunk[3];
+    int64_t rb[3], re[3], nchunk[3];
+    tile_event_ranges(ranges, blockIdx.y, blockIdx.x, nsub, rsub, rb, re);
     int total_chunks = 0;
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
-        rb[m] = rg[2 * m];
-        const int64_t ne = rg[2 * m + 1] - rb[m];
+        const int64_t ne = re[m] - rb[m];
         nchunk[m] = (ne + EC - 1) / EC;
         total_chunks += (int)nchunk[m];
     }
@@ -430,7 +445,7 @@ __global__ __launch_bounds__(256) void k_spread(const double* __restrict__ t, co
         m = 0;
         while (q >= nchunk[m]) { q -= (int)nchunk[m]; ++m; }
         cb = rb[m] + (int64_t)q * EC;
-        n = (int)min((int64_t)EC, rg[2 * m + 1] - cb);
+        n = (int)min((int64_t)EC, re[m] - cb);
     };
     T acc[CPT];
 #pragma unroll
@@ -532,8 +547,9 @@ __global__ __launch_bounds__(256) void k_spread(const double* __restrict__ t, co
 template <typename DPT, int W, int PPT>
 __global__ __launch_bounds__(256) void k_spread_poly(const double* __restrict__ t, const DPT* __restrict__ dp,
                                                      double t0, double scale, int Mr, double hw, PolyParams pp,
-                                                     const int64_t* __restrict__ ranges, int tiles, int L2, int L2p,
-                                                     FastDiv divL2, float* __restrict__ grid, int64_t grid_stride)
+                                                     const int64_t* __restrict__ ranges, int nsub, int rsub,
+                                                     float dmin, int L2, int L2p, FastDiv divL2,
+                                                     float* __restrict__ grid, int64_t grid_stride)
 {
     constexpr int TC = 512 * PPT;
     constexpr int M = (W + 2) & ~1;                      // even ring, >= W + 1
@@ -545,21 +561,23 @@ __global__ __launch_bounds__(256) void k_spread_poly(const double* __restrict__ 
     __shared__ unsigned short first[TC + W + 2];
     const int a = blockIdx.x * TC;
     const int len = min(TC, Mr - a);
-    const int64_t* rg = ranges + ((int64_t)blockIdx.y * tiles + blockIdx.x) * 6;
-    int64_t rb[3], nchunk[3];
+    int64_t rb[3], re[3], nchunk[3];
+    tile_event_ranges(ranges, blockIdx.y, blockIdx.x, nsub, rsub, rb, re);
     int total_chunks = 0;
+    int64_t n_tile = 0;
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
-        rb[m] = rg[2 * m];
-        const int64_t ne = rg[2 * m + 1] - rb[m];
+        const int64_t ne = re[m] - rb[m];
+        n_tile += ne;
         nchunk[m] = (ne + EC - 1) / EC;
         total_chunks += (int)nchunk[m];
     }
+    if ((float)n_tile >= dmin * (float)len) return;   // a dense tile: k_spread_mom's
     auto locate = [&](int q, int64_t& cb, int& n, int& m) {
         m = 0;
         while (q >= nchunk[m]) { q -= (int)nchunk[m]; ++m; }
         cb = rb[m] + (int64_t)q * EC;
-        n = (int)min((int64_t)EC, rg[2 * m + 1] - cb);
+        n = (int)min((int64_t)EC, re[m] - cb);
     };
     float acc0[PPT], acc1[PPT];
 #pragma unroll
@@ -703,31 +721,279 @@ __global__ __launch_bounds__(256) void k_spread_poly(const double* __restrict__ 
     }
 }
 
+// Dense tiles: the same sum from per-cell moments.  Tap j of an event with offset
+// s = f - 1/2 and return v is v p_j(s) = sum_d c_jd v s^d, so the events whose
+// first tap is cell l give cell l + j the amount sum_d c_jd M_l[d], with the
+// moments M_l[d] = sum over those events of v s^d, and
+//   x_c = sum_{j < W} sum_{d <= DEG} c_jd M_{c-j}[d].
+// Per event that is DEG multiplies and DEG+1 adds (no taps, no ring, no gather);
+// per cell W (DEG+1) multiply-adds, so it pays once a tile holds more than about
+// one event per cell.  This kernel takes the tiles with at least dmin events per
+// cell and k_spread_poly the others (the same test in both).  A tile of tc cells
+// runs as sub-tiles of kMomCells cells, each in three steps:
+//   1. the sub-tile's event ranges (from the set-up's search, which is done per
+//      sub-tile of kRangeCells cells);
+//   2. per staged chunk ((s, v) in LDS, the first event of every key; the next
+//      chunk's loads in flight meanwhile), thread t sums in registers the moments
+//      of keys t, t + 256, t + 512, t + 768 over their events; the last W-1 keys
+//      (past kMomCells) are summed into LDS by threads 0..W-2;
+//   3. the moments go to LDS (over the staging buffers), and thread t forms cells
+//      4t..4t+3 from keys 4t..4t+3+W-1.
+// A key is the event's first-tap cell minus (b - W + 1), b the sub-tile's first
+// cell: cell c of the sub-tile takes tap j from key c + W - 1 - j.  Every sum has
+// a fixed order (events in time order per key, then d, then j), so results are
+// reproducible bit for bit.
+constexpr int kMomCells = 1024;   // cells of a sub-tile: 4 per thread
+constexpr int kMomEV = 4;         // events per thread per staged chunk
+
+template <int W>
+struct MomLds {
+    static constexpr int DEG = poly_degree_for_width(W);
+    static constexpr int ND = DEG + 1;                          // moments per key (<= 9)
+    static constexpr int NKP = kMomCells + 16;                  // keys, padded (W <= 17)
+    static constexpr int EC = kMomEV * 256;                     // events per chunk
+    static constexpr int stage_bytes = 8 * EC + 2 * EC + 2 * (NKP + 2);
+    static constexpr int mom_bytes = 36 * NKP;                  // per key: d 0-3, d 4-7 (float4), d 8
+    static constexpr int bytes = stage_bytes > mom_bytes ? stage_bytes : mom_bytes;
+};
+
+template <typename DPT, int W>
+__global__ __launch_bounds__(256) void k_spread_mom(const double* __restrict__ t, const DPT* __restrict__ dp,
+                                                    double t0, double scale, int Mr, double hw, PolyParams pp,
+                                                    const int64_t* __restrict__ ranges, int nsub, int rsub, int tc,
+                                                    float dmin, int L2, int L2p, FastDiv divL2,
+                                                    float* __restrict__ grid, int64_t grid_stride)
+{
+    using Lay = MomLds<W>;
+    constexpr int ND = Lay::ND, NKP = Lay::NKP, EC = Lay::EC;
+    constexpr int H = (W + 1) / 2;                              // taps with stored coefficients
+    static_assert(W >= 2 && W <= 17 && ND <= 9, "key padding, moment layout");
+    __shared__ __align__(16) char lds[Lay::bytes];
+    __shared__ float hmom[16 * ND];                             // keys kMomCells.. (their owners: threads 0..W-2)
+    float2* const sv = reinterpret_cast<float2*>(lds);                              // staging: (s, v)
+    unsigned short* const keys = reinterpret_cast<unsigned short*>(lds + 8 * EC);   // staging: keys
+    unsigned short* const first = keys + EC;                                        // first event of a key
+    float4* const momA = reinterpret_cast<float4*>(lds);                            // moments d 0-3
+    float4* const momB = momA + NKP;                                                // d 4-7
+    float* const momC = reinterpret_cast<float*>(momB + NKP);                       // d 8
+
+    const int a = blockIdx.x * tc;
+    const int len = min(tc, Mr - a);
+    {
+        int64_t tb[3], te[3], n_tile = 0;
+        tile_event_ranges(ranges, blockIdx.y, blockIdx.x, nsub, rsub, tb, te);
+#pragma unroll
+        for (int m = 0; m < 3; ++m) n_tile += te[m] - tb[m];
+        if (!((float)n_tile >= dmin * (float)len)) return;     // a sparse tile: k_spread_poly's
+    }
+    const int tid = threadIdx.x;
+    float2* out = reinterpret_cast<float2*>(grid + (int64_t)blockIdx.y * grid_stride);
+
+    static_assert(kMomCells == kRangeCells, "a sub-tile has its own event ranges");
+    for (int b0 = 0, h = 0; b0 < len; b0 += kMomCells, ++h) {
+        const int b = a + b0;
+        const int lenh = min(kMomCells, len - b0);
+        // 1. the sub-tile's event ranges (first-tap cells in [b + m' Mr - W + 1, b + lenh + m' Mr),
+        //    m' = m - 1), from the set-up's search
+        const int64_t* sr = ranges + ((int64_t)blockIdx.y * nsub + (int64_t)blockIdx.x * rsub + h) * 6;
+        for (int i = tid; i < 16 * ND; i += 256) hmom[i] = 0.f;
+        __syncthreads();
+        int64_t rb[3], re[3], nchunk[3];
+        int total_chunks = 0;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            rb[m] = sr[2 * m];
+            re[m] = max(sr[2 * m + 1], rb[m]);
+            nchunk[m] = (re[m] - rb[m] + EC - 1) / EC;
+            total_chunks += (int)nchunk[m];
+        }
+        auto locate = [&](int q, int64_t& cb, int& n, int& m) {
+            m = 0;
+            while (q >= nchunk[m]) { q -= (int)nchunk[m]; ++m; }
+            cb = rb[m] + (int64_t)q * EC;
+            n = (int)min((int64_t)EC, re[m] - cb);
+        };
+        // the chunk's loads are unconditional (past its end they repeat its last event)
+        double tv[kMomEV];
+        DPT dv[kMomEV];
+        auto load_chunk = [&](int q) {
+            int64_t cb; int n, m;
+            locate(min(q, total_chunks - 1), cb, n, m);
+#pragma unroll
+            for (int u = 0; u < kMomEV; ++u) {
+                const int64_t ii = cb + min(tid + 256 * u, n - 1);
+                tv[u] = t[ii];
+                dv[u] = dp[ii];
+            }
+        };
+        float acc[4][ND];
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+#pragma unroll
+            for (int d = 0; d < ND; ++d) acc[g][d] = 0.f;
+        if (total_chunks > 0) load_chunk(0);
+
+        // 2. chunks of staged events
+        for (int q = 0; q < total_chunks; ++q) {
+            int64_t cb; int n, m;
+            locate(q, cb, n, m);
+            // key = first-tap cell - (b + (m - 1) Mr) + W - 1, the first-tap cell being floor(g - hw) + 1
+            const int kofs = (int)((int64_t)W - (int64_t)b - (int64_t)(m - 1) * Mr);
+            __syncthreads();   // the previous chunk's staging is read out
+#pragma unroll
+            for (int u = 0; u < kMomEV; ++u) {
+                const int i = tid + 256 * u;
+                if (i < n) {
+                    const double tt = fma(__dsub_rn(tv[u], t0), scale, -hw);
+                    const double fl = floor(tt);
+                    const double f = __dsub_rn(tt, fl);
+                    sv[i] = make_float2((float)(f - 0.5), (float)dv[u]);
+                    keys[i] = (unsigned short)((int)fl + kofs);
+                }
+            }
+            if (q + 1 < total_chunks) load_chunk(q + 1);   // in flight while this chunk is summed
+            __syncthreads();
+            const int kmin = __builtin_amdgcn_readfirstlane(keys[0]);
+            const int kmax = __builtin_amdgcn_readfirstlane(keys[n - 1]);
+            for (int i = 1 + tid; i < n; i += 256) {
+                const int k1 = keys[i];
+                for (int k = keys[i - 1] + 1; k <= k1; ++k) first[k] = (unsigned short)i;
+            }
+            __syncthreads();
+            // events of key k: [k <= kmin ? 0 : first[k], k >= kmax ? n : first[k + 1]), summed
+            // in time order; four events' (s, v) are read at once, so their LDS reads
+            // overlap (the adds stay in event order)
+            auto add_event = [&](float2 x, float (&ac)[ND]) {
+                float pw = x.y;
+#pragma unroll
+                for (int d = 0; d < ND; ++d) {
+                    ac[d] += pw;
+                    if (d + 1 < ND) pw *= x.x;
+                }
+            };
+            auto sum_key = [&](int k, float (&ac)[ND]) {
+                const int lo = (k <= kmin) ? 0 : first[k];
+                const int hi = (k >= kmax) ? n : first[k + 1];
+                int e = lo;
+                for (; e + 3 < hi; e += 4) {
+                    const float2 x0 = sv[e], x1 = sv[e + 1], x2 = sv[e + 2], x3 = sv[e + 3];
+                    add_event(x0, ac);
+                    add_event(x1, ac);
+                    add_event(x2, ac);
+                    add_event(x3, ac);
+                }
+                for (; e < hi; ++e) add_event(sv[e], ac);
+            };
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const int k = tid + 256 * g;
+                if (k >= kmin && k <= kmax) sum_key(k, acc[g]);
+            }
+            if (tid < W - 1) {
+                const int k = kMomCells + tid;
+                if (k >= kmin && k <= kmax) {
+                    float h[ND];
+#pragma unroll
+                    for (int d = 0; d < ND; ++d) h[d] = hmom[tid * ND + d];
+                    sum_key(k, h);
+#pragma unroll
+                    for (int d = 0; d < ND; ++d) hmom[tid * ND + d] = h[d];
+                }
+            }
+        }
+        // 3. moments to LDS (over the staging buffers), then the cells
+        __syncthreads();
+        auto put = [&](int k, const float* mv) {
+            float v[9];
+#pragma unroll
+            for (int d = 0; d < 9; ++d) v[d] = d < ND ? mv[d] : 0.f;
+            momA[k] = make_float4(v[0], v[1], v[2], v[3]);
+            momB[k] = make_float4(v[4], v[5], v[6], v[7]);
+            momC[k] = v[8];
+        };
+#pragma unroll
+        for (int g = 0; g < 4; ++g) put(tid + 256 * g, acc[g]);
+        if (tid < 16) {
+            float h[ND];
+#pragma unroll
+            for (int d = 0; d < ND; ++d) h[d] = tid < W - 1 ? hmom[tid * ND + d] : 0.f;
+            put(kMomCells + tid, h);
+        }
+        __syncthreads();
+        if (4 * tid < lenh) {
+            float x[4] = {0.f, 0.f, 0.f, 0.f};
+            // keys 4t + kk, kk = 0 .. W + 2, one at a time (a uniform loop: the
+            // coefficients are scalar loads)
+#pragma unroll 1
+            for (int kk = 0; kk < W + 3; ++kk) {
+                const int k = 4 * tid + kk;
+                const float4 A = momA[k], B = momB[k];
+                const float m8 = momC[k];
+                const float mv[9] = {A.x, A.y, A.z, A.w, B.x, B.y, B.z, B.w, m8};
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int j = r + W - 1 - kk;               // tap of key 4t + kk reaching cell 4t + r
+                    if (j < 0 || j >= W) continue;
+                    const bool mir = j >= H;                    // the mirror of stored tap W-1-j: (-1)^d
+                    const int js = mir ? W - 1 - j : j;
+#pragma unroll
+                    for (int d = 0; d < ND; ++d) {
+                        const float c = pp.c[js][d];
+                        x[r] = fmaf((mir && (d & 1)) ? -c : c, mv[d], x[r]);
+                    }
+                }
+            }
+            // cells (4t, 4t+1) and (4t+2, 4t+3): complex entries (b + 4t)/2 and (b + 4t)/2 + 1
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                if (4 * tid + 2 * h < lenh) {
+                    const int j = (b + 4 * tid) / 2 + h;
+                    const int row = (int)fdiv((uint32_t)j, divL2);
+                    out[(int64_t)row * L2p + (j - row * L2)] = make_float2(x[2 * h], x[2 * h + 1]);
+                }
+            }
+        }
+        __syncthreads();   // the moments are read out before the next sub-tile stages over them
+    }
+}
+
 template <typename DPT, int W>
 static void spread_poly_w(const Plan& p, dim3 g, const double* t, const DPT* dp, double t0, double scale,
-                          const int64_t* ranges, int tiles, float* grid, int64_t gs, hipStream_t st)
+                          const int64_t* ranges, int nsub, float* grid, int64_t gs, hipStream_t st)
 {
+    const int rsub = p.tile / kRangeCells;
     const FastDiv dv = make_fastdiv((uint32_t)p.L2);
+    // tiles with at least dmin events per cell go to the moment kernel (none if it is off)
+    const bool mom = p.mom_density > 0.0 && W <= 17;
+    const float dmin = mom ? (float)p.mom_density : __builtin_huge_valf();
+    prof_begin("k_spread_poly", st);
     if (p.tile <= 1024)
         hipLaunchKernelGGL((k_spread_poly<DPT, W, 2>), g, dim3(256), 0, st, t, dp, t0, scale, p.Mr, p.kp.hw, p.pp,
-                           ranges, tiles, p.L2, p.L2p, dv, grid, gs);
+                           ranges, nsub, rsub, dmin, p.L2, p.L2p, dv, grid, gs);
     else if (p.tile <= 2048)
         hipLaunchKernelGGL((k_spread_poly<DPT, W, 4>), g, dim3(256), 0, st, t, dp, t0, scale, p.Mr, p.kp.hw, p.pp,
-                           ranges, tiles, p.L2, p.L2p, dv, grid, gs);
+                           ranges, nsub, rsub, dmin, p.L2, p.L2p, dv, grid, gs);
     else
         hipLaunchKernelGGL((k_spread_poly<DPT, W, 8>), g, dim3(256), 0, st, t, dp, t0, scale, p.Mr, p.kp.hw, p.pp,
-                           ranges, tiles, p.L2, p.L2p, dv, grid, gs);
+                           ranges, nsub, rsub, dmin, p.L2, p.L2p, dv, grid, gs);
+    prof_end("k_spread_poly", st);
+    if (mom) {
+        prof_begin("k_spread_mom", st);
+        hipLaunchKernelGGL((k_spread_mom<DPT, W>), g, dim3(256), 0, st, t, dp, t0, scale, p.Mr, p.kp.hw, p.pp, ranges,
+                           nsub, rsub, p.tile, dmin, p.L2, p.L2p, dv, grid, gs);
+        prof_end("k_spread_mom", st);
+    }
 }
 
 template <typename DPT>
 static hipError_t spread_poly_t(const Plan& p, int s_count, const double* t, const DPT* dp, double t0, double t_end,
-                                const int64_t* ranges, int tiles, float* grid, int64_t gs, hipStream_t st)
+                                const int64_t* ranges, int nsub, float* grid, int64_t gs, hipStream_t st)
 {
     const double span = t_end - t0;
     const double scale = (double)p.Mr / span;
-    const dim3 g(tiles, s_count);
+    const dim3 g((p.Mr + p.tile - 1) / p.tile, s_count);
     switch (p.kp.w) {
-#define MM_POLY_W(n) case n: spread_poly_w<DPT, n>(p, g, t, dp, t0, scale, ranges, tiles, grid, gs, st); break;
+#define MM_POLY_W(n) case n: spread_poly_w<DPT, n>(p, g, t, dp, t0, scale, ranges, nsub, grid, gs, st); break;
         MM_POLY_W(2) MM_POLY_W(3) MM_POLY_W(4) MM_POLY_W(5) MM_POLY_W(6) MM_POLY_W(7) MM_POLY_W(8) MM_POLY_W(9)
         MM_POLY_W(10) MM_POLY_W(11) MM_POLY_W(12) MM_POLY_W(13) MM_POLY_W(14) MM_POLY_W(15) MM_POLY_W(16)
 #undef MM_POLY_W
@@ -737,13 +1003,13 @@ static hipError_t spread_poly_t(const Plan& p, int s_count, const double* t, con
 }
 
 hipError_t launch_spread_poly(const Plan& p, int s_count, const double* t, const void* dp, int dp_fp64, double t0,
-                              double t_end, const int64_t* ranges, int tiles, float* grid, int64_t grid_stride,
+                              double t_end, const int64_t* ranges, int nsub, float* grid, int64_t grid_stride,
                               hipStream_t st)
 {
     if (dp_fp64)
-        return spread_poly_t<double>(p, s_count, t, (const double*)dp, t0, t_end, ranges, tiles, grid, grid_stride,
+        return spread_poly_t<double>(p, s_count, t, (const double*)dp, t0, t_end, ranges, nsub, grid, grid_stride,
                                      st);
-    return spread_poly_t<float>(p, s_count, t, (const float*)dp, t0, t_end, ranges, tiles, grid, grid_stride, st);
+    return spread_poly_t<float>(p, s_count, t, (const float*)dp, t0, t_end, ranges, nsub, grid, grid_stride, st);
 }
 
 constexpr int kBatch = 8;   // independent global loads a thread issues before consuming them
@@ -1144,32 +1410,33 @@ hipError_t launch_validate(int32_t S, const int64_t* offsets, const double* t, c
 
 template <typename T, typename DPT, int KIND>
 static void launch_spread_t(const Plan& p, int s_count, const double* t, const DPT* dp, double t0, double t_end,
-                            const int64_t* ranges, int tiles, T* grid, int64_t grid_stride, hipStream_t st)
+                            const int64_t* ranges, int nsub, T* grid, int64_t grid_stride, hipStream_t st)
 {
     const double span = t_end - t0;
     const double scale = (double)p.Mr / span;
-    const dim3 g(tiles, s_count);
+    const dim3 g((p.Mr + p.tile - 1) / p.tile, s_count);
+    const int rsub = p.tile / kRangeCells;
     if (p.tile <= 1024)
         hipLaunchKernelGGL((k_spread<T, DPT, KIND, 4>), g, dim3(256), 0, st, t, dp, t0, span, scale, p.kp, p.Mr,
-                           ranges, tiles, p.L2, p.L2p, make_fastdiv((uint32_t)p.L2), grid, grid_stride);
+                           ranges, nsub, rsub, p.L2, p.L2p, make_fastdiv((uint32_t)p.L2), grid, grid_stride);
     else if (p.tile <= 2048)
         hipLaunchKernelGGL((k_spread<T, DPT, KIND, 8>), g, dim3(256), 0, st, t, dp, t0, span, scale, p.kp, p.Mr,
-                           ranges, tiles, p.L2, p.L2p, make_fastdiv((uint32_t)p.L2), grid, grid_stride);
+                           ranges, nsub, rsub, p.L2, p.L2p, make_fastdiv((uint32_t)p.L2), grid, grid_stride);
     else
         hipLaunchKernelGGL((k_spread<T, DPT, KIND, 16>), g, dim3(256), 0, st, t, dp, t0, span, scale, p.kp,
-                           p.Mr, ranges, tiles, p.L2, p.L2p, make_fastdiv((uint32_t)p.L2), grid, grid_stride);
+                           p.Mr, ranges, nsub, rsub, p.L2, p.L2p, make_fastdiv((uint32_t)p.L2), grid, grid_stride);
 }
 
 template <typename T, typename DPT>
 static void launch_spread_k(const Plan& p, int s_count, const double* t, const DPT* dp, double t0, double t_end,
-                            const int64_t* ranges, int tiles, T* grid, int64_t grid_stride, hipStream_t st)
+                            const int64_t* ranges, int nsub, T* grid, int64_t grid_stride, hipStream_t st)
 {
     if (p.kernel == MM_ES)
-        launch_spread_t<T, DPT, MM_ES>(p, s_count, t, dp, t0, t_end, ranges, tiles, grid, grid_stride, st);
+        launch_spread_t<T, DPT, MM_ES>(p, s_count, t, dp, t0, t_end, ranges, nsub, grid, grid_stride, st);
     else if (p.kernel == MM_GAUSSIAN)
-        launch_spread_t<T, DPT, MM_GAUSSIAN>(p, s_count, t, dp, t0, t_end, ranges, tiles, grid, grid_stride, st);
+        launch_spread_t<T, DPT, MM_GAUSSIAN>(p, s_count, t, dp, t0, t_end, ranges, nsub, grid, grid_stride, st);
     else
-        launch_spread_t<T, DPT, MM_KAISER_BESSEL>(p, s_count, t, dp, t0, t_end, ranges, tiles, grid, grid_stride, st);
+        launch_spread_t<T, DPT, MM_KAISER_BESSEL>(p, s_count, t, dp, t0, t_end, ranges, nsub, grid, grid_stride, st);
 }
 
 static int ilog2(int x)
@@ -1205,31 +1472,31 @@ static hipError_t nufft_tiled_t(const Plan& p, const NufftWs& w, char* ws, int32
     using C = typename CT<T>::type;
     T* grid = (T*)(ws + w.grid);
     const int64_t gstride = 2ll * p.L1 * p.L2p;
-    const int tiles = (p.Mr + p.tile - 1) / p.tile;
+    // event ranges per sub-tile of kRangeCells cells, nsub per series
+    const int nsub = (p.Mr + kRangeCells - 1) / kRangeCells;
     int64_t* ranges = (int64_t*)(ws + w.ranges);
     if (!ranges_ready) {
-        hipError_t er = launch_tile_ranges(p, offsets, t, s_begin, s_count, tiles, p.tile, t0, T_, ranges, st);
+        hipError_t er = launch_tile_ranges(p, offsets, t, s_begin, s_count, nsub, kRangeCells, t0, T_, ranges, st);
         if (er != hipSuccess) return er;
     }
-    // recorded under the name of the kernel that runs
-    const char* spread_name = (sizeof(T) == 4 && p.poly) ? "k_spread_poly" : "k_spread";
-    prof_begin(spread_name, st);
+    // recorded under the name of the kernel that runs (the polynomial path names its
+    // own, one per kernel)
+    bool spread_done = false;
     if constexpr (sizeof(T) == 4) {
         if (p.poly) {
-            hipError_t e = launch_spread_poly(p, s_count, t, dp, dp_fp64, t0, T_, ranges, tiles, grid, gstride, st);
+            hipError_t e = launch_spread_poly(p, s_count, t, dp, dp_fp64, t0, T_, ranges, nsub, grid, gstride, st);
             if (e != hipSuccess) return e;
-        } else if (dp_fp64) {
-            launch_spread_k<T, double>(p, s_count, t, (const double*)dp, t0, T_, ranges, tiles, grid, gstride, st);
-        } else {
-            launch_spread_k<T, float>(p, s_count, t, (const float*)dp, t0, T_, ranges, tiles, grid, gstride, st);
+            spread_done = true;
         }
-    } else {
-        if (dp_fp64)
-            launch_spread_k<T, double>(p, s_count, t, (const double*)dp, t0, T_, ranges, tiles, grid, gstride, st);
-        else
-            launch_spread_k<T, float>(p, s_count, t, (const float*)dp, t0, T_, ranges, tiles, grid, gstride, st);
     }
-    prof_end(spread_name, st);
+    if (!spread_done) {
+        prof_begin("k_spread", st);
+        if (dp_fp64)
+            launch_spread_k<T, double>(p, s_count, t, (const double*)dp, t0, T_, ranges, nsub, grid, gstride, st);
+        else
+            launch_spread_k<T, float>(p, s_count, t, (const float*)dp, t0, T_, ranges, nsub, grid, gstride, st);
+        prof_end("k_spread", st);
+    }
 
     if (p.fft_ab) return launch_fft_ab(p, w, ws, s_begin, s_count, grid, gstride, coef, ldc, st, so);
     if (so) return hipErrorInvalidValue;   // the split is fused only into the two-pass FFT

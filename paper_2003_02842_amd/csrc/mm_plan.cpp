@@ -287,7 +287,7 @@ static double estimate_error_uncached(const KernParams& kp, int Mr, int N)
 // Gaussian formula and 6.5-9.8 with the Kaiser-Bessel formula.
 static double rounding_gain(int kernel, bool poly)
 {
-    if (poly) return 2.0;
+    if (poly) return 3.0;   // per-event taps 2.0; the per-cell moment form up to 1.5x that
     if (kernel == MM_KAISER_BESSEL) return 10.0;
     return kernel == MM_GAUSSIAN ? 6.5 : 4.5;
 }
@@ -567,6 +567,11 @@ mm_status make_plan(int32_t N, mm_kernel kernel, double tol, mm_prec prec, const
     int tile = (prec == MM_MIXED) ? 2048 : 1024;
     if (tune && tune->tile > 0) tile = tune->tile <= 1024 ? 1024 : (tune->tile <= 2048 ? 2048 : 4096);
     p->tile = tile;
+    // dense tiles from per-cell moments (the per-tap polynomials' coefficients, up to 17 taps)
+    {
+        const double md = tune ? tune->moment_density : 0.0;
+        p->mom_density = (p->poly && p->kp.w <= 17 && md >= 0.0) ? (md > 0.0 ? md : kMomDensity) : 0.0;
+    }
     // the fused single-workgroup NUFFT of small grids: 0 (auto) for calls of at least
     // kFusedMinSeries series, 1 for any call, -1 never
     const int fz = tune ? tune->fused : 0;
@@ -596,7 +601,7 @@ NufftWs nufft_workspace(const Plan& p, int32_t S)
     w.flag = o; o += 256;
     const bool fused = use_fused(p, S);
     w.S_grid = fused ? 0 : (p.prec == MM_MIXED ? S : 1);
-    const size_t tiles = (size_t)(p.Mr + p.tile - 1) / p.tile;
+    const size_t tiles = (size_t)(p.Mr + kRangeCells - 1) / kRangeCells;   // event-range sub-tiles
     w.ranges = o; o += al(8 * 6 * (fused ? (size_t)S : tiles * (size_t)w.S_grid));
     w.grid = o; o += al(rs * 2 * (size_t)p.L1 * (size_t)p.L2p * (size_t)w.S_grid);
     w.total = o;

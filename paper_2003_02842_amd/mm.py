@@ -46,7 +46,8 @@ class CsrInfo(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("width", ctypes.c_int32), ("sigma", ctypes.c_double), ("tile", ctypes.c_int32),
                 ("fused", ctypes.c_int32), ("es_beta_per_tap", ctypes.c_double), ("fft_generic", ctypes.c_int32),
-                ("spread_direct", ctypes.c_int32), ("syrk_tile", ctypes.c_int32), ("syrk_splits", ctypes.c_int32)]
+                ("spread_direct", ctypes.c_int32), ("syrk_tile", ctypes.c_int32), ("syrk_splits", ctypes.c_int32),
+                ("moment_density", ctypes.c_double)]
 
 
 class PlanInfo(ctypes.Structure):

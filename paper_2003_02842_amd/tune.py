@@ -27,14 +27,18 @@ from paper_2003_02842_amd import mm
 
 # The autotuner's pick on MI355X for the large-universe workload (2000 series,
 # counts log-uniform in [1e4, 1e6], N = 50,000, ES, tol 1e-6, Fejer), from
-# `python -m paper_2003_02842_amd.tune` over 60 candidates: sigma 1.55 (w = 9,
-# Mr = 155,520), per-tap polynomials, 2048-cell tiles, 3.82 ms per NUFFT against
-# 4.21 ms at the planner's default sigma = 2 (w = 8).
-LARGE_UNIVERSE = {"sigma": 1.55, "spread_direct": 2, "tile": 2048}
+# `python -m paper_2003_02842_amd.tune` over 72 NUFFT candidates: sigma 1.55
+# (w = 9, Mr = 155,520), per-tap polynomials, 2048-cell tiles, moments from 4
+# events per cell, 3.77 ms per NUFFT against 4.21 ms at the planner's default
+# sigma = 2 (w = 8).  The full pick, with the contraction's, is in tuned_plans.json.
+LARGE_UNIVERSE = {"sigma": 1.55, "spread_direct": 2, "tile": 2048, "moment_density": 4.0}
 
 SIGMAS = (1.25, 1.4, 1.5, 1.55, 1.6, 1.65, 1.75, 2.0, 2.25, 2.5)
 TILES = (1024, 2048, 4096)
 EVALS = (1, 2)   # mm_tuning.spread_direct: 1 kernel formula per pair, 2 per-tap polynomials
+# mm_tuning.moment_density with per-tap polynomials: -1 per-event taps only, else the
+# events per cell from which a tile spreads from per-cell moments
+MOMENTS = (-1.0, 2.0, 3.0, 4.0)
 
 
 def _key(S, E, N, kernel, tol, basis):
@@ -59,13 +63,13 @@ def _time_ms(fn, reps):
 
 def autotune(offsets, t, dp, t0: float, T: float, N: int, kernel="es", tol: float = 1e-6, basis="fejer",
              sigma_tol: float = 1e-5, calib_series: int = 16, sigmas=SIGMAS, tiles=TILES, evals=EVALS,
-             reps: int = 3, cache_path: str = None, verbose: bool = False) -> dict:
+             moments=MOMENTS, reps: int = 3, cache_path: str = None, verbose: bool = False) -> dict:
     """Fastest admitted mm_tuning (as a dict with the chosen plan) for
     mm_nufft1(offsets, t, dp, t0, T, N, kernel, tol, "mixed").
 
     The calibration subset is the ``calib_series`` series with the most events
-    (the hardest for the FP32 sums); its FP64 reference uses the same kernel at
-    tol 1e-12."""
+    (the hardest for the FP32 sums, and dense enough to take the per-cell moment
+    path); its FP64 reference uses the same kernel at tol 1e-12."""
     S = offsets.numel() - 1
     E = int(offsets[-1])
     key = _key(S, E, N, kernel, tol, basis)
@@ -91,30 +95,30 @@ def autotune(offsets, t, dp, t0: float, T: float, N: int, kernel="es", tol: floa
     S_ref = S_ref.double()
     results = []
     out = torch.empty((S, N + 1), dtype=torch.complex64, device=t.device)
-    for sg in sigmas:
-        for ev in evals:
-            base = {"sigma": float(sg), "spread_direct": int(ev)}
-            try:
-                plan = mm.plan_query(N, kernel, tol, "mixed", base)
-            except mm.MMError:
-                continue
-            cc = mm.nufft1(oc, tc, dc, t0, T, N, kernel, tol, "mixed", base)
-            Sm, _ = mm.cov(cc, 1, D, [N], basis, correlation=False)
-            err = float(torch.linalg.norm((Sm.double() - S_ref).flatten()) / torch.linalg.norm(S_ref.flatten()))
-            if not err <= sigma_tol:
-                if verbose:
-                    print("tune: sigma %.2f eval %d rejected (err %.2e)" % (sg, ev, err), flush=True)
-                continue
-            for tile in tiles:
-                tune = dict(base, tile=int(tile))
-                ws = torch.empty(mm.nufft1_workspace_size(S, N, kernel, tol, "mixed", tune), dtype=torch.uint8,
-                                 device=t.device)
-                ms = _time_ms(lambda: mm.nufft1(offsets, t, dp, t0, T, N, kernel, tol, "mixed", tune, out=out, ws=ws),
-                              reps)
-                del ws
-                results.append((ms, tune, plan, err))
-                if verbose:
-                    print("tune: %s width %d Mr %d: %.3f ms (err %.2e)" % (tune, plan["width"], plan["Mr"], ms, err), flush=True)
+    cands = [(sg, ev, md) for sg in sigmas for ev in evals for md in (moments if ev == 2 else (-1.0,))]
+    for sg, ev, md in cands:
+        base = {"sigma": float(sg), "spread_direct": int(ev), "moment_density": float(md)}
+        try:
+            plan = mm.plan_query(N, kernel, tol, "mixed", base)
+        except mm.MMError:
+            continue
+        cc = mm.nufft1(oc, tc, dc, t0, T, N, kernel, tol, "mixed", base)
+        Sm, _ = mm.cov(cc, 1, D, [N], basis, correlation=False)
+        err = float(torch.linalg.norm((Sm.double() - S_ref).flatten()) / torch.linalg.norm(S_ref.flatten()))
+        if not err <= sigma_tol:
+            if verbose:
+                print("tune: sigma %.2f eval %d moments %g rejected (err %.2e)" % (sg, ev, md, err), flush=True)
+            continue
+        for tile in tiles:
+            tune = dict(base, tile=int(tile))
+            ws = torch.empty(mm.nufft1_workspace_size(S, N, kernel, tol, "mixed", tune), dtype=torch.uint8,
+                             device=t.device)
+            ms = _time_ms(lambda: mm.nufft1(offsets, t, dp, t0, T, N, kernel, tol, "mixed", tune, out=out, ws=ws),
+                          reps)
+            del ws
+            results.append((ms, tune, plan, err))
+            if verbose:
+                print("tune: %s width %d Mr %d: %.3f ms (err %.2e)" % (tune, plan["width"], plan["Mr"], ms, err), flush=True)
     if not results:
         raise RuntimeError("no candidate met the accuracy target")
     ms, tune, plan, err = min(results, key=lambda r: r[0])
@@ -194,7 +198,7 @@ def main(argv=None):
     a = ap.parse_args(argv)
     w = synth.large_universe(D=a.D, N=a.N, device="cuda")
     best = autotune(w.offsets, w.t, w.dp, w.t0, w.T, a.N, "es", a.tol, "fejer", reps=a.reps, verbose=True,
-                    sigmas=tuple(float(x) for x in a.sigmas.split(",")), tiles=(2048, 4096), evals=(2,))
+                    sigmas=tuple(float(x) for x in a.sigmas.split(",")), tiles=(1024, 2048, 4096), evals=(2,))
     coef = mm.nufft1(w.offsets, w.t, w.dp, w.t0, w.T, a.N, "es", a.tol, "mixed", best["tuning"])
     con = autotune_contraction(coef, w.S, a.N, "fejer", reps=a.reps, verbose=True)
     tuning = dict(best["tuning"], syrk_tile=con["syrk_tile"], syrk_splits=con["syrk_splits"])

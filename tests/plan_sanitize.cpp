@@ -59,6 +59,7 @@ static void check_plan(const Plan& p, int N, int kernel, double tol, int prec, c
               fft_ab_lds_cols(p), fft_ab_lds_rows(p));
         CHECK(p.CC >= 1 && p.RR >= 1, "CC %d RR %d", p.CC, p.RR);
     }
+    CHECK(p.mom_density == 0.0 || (p.poly && p.kp.w <= 17), "moments without polynomials (w %d)", p.kp.w);
     if (p.fused) {
         CHECK(p.Mr <= kFusedMaxCells && fused_lds_bytes(p) <= kFusedMaxLds, "fused plan Mr %d LDS %zu", p.Mr,
               fused_lds_bytes(p));
@@ -105,7 +106,8 @@ int main()
                         for (int tile : {0, 1024, 4096})
                             for (int fz : {-1, 0, 1})
                                 for (double tol : {1e-4, 1e-6}) {
-                                    mm_tuning t = {width, sg, tile, fz, 0.0, fz == 1, sd, 0, 0};
+                                    const double md = fz == 1 ? 2.5 : (fz == -1 ? -1.0 : 0.0);
+                                    mm_tuning t = {width, sg, tile, fz, 0.0, fz == 1, sd, 0, 0, md};
                                     run(N, k, tol, MM_MIXED, &t);
                                     if (sd == 0 && fz == 0) run(N, k, tol * 1e-4, MM_PLAIN_FP64, &t);
                                 }
@@ -119,7 +121,7 @@ int main()
         CHECK(make_plan(100, MM_ES, nan(""), MM_MIXED, nullptr, &p) == MM_ERR_TOL, "NaN tol accepted");
         CHECK(make_plan(100, MM_ES, 1e-7, MM_MIXED, nullptr, &p) == MM_ERR_TOL, "mixed tol below 1e-6 accepted");
         CHECK(make_plan(100, MM_ES, 0.5, MM_PLAIN_FP64, nullptr, &p) == MM_ERR_TOL, "tol 0.5 accepted");
-        mm_tuning t = {0, 1.0, 0, 0, 0.0, 0, 0, 0, 0};
+        mm_tuning t = {0, 1.0, 0, 0, 0.0, 0, 0, 0, 0, 0.0};
         CHECK(make_plan(100, MM_ES, 1e-6, MM_MIXED, &t, &p) == MM_ERR_ARG, "sigma 1 accepted");
         t.sigma = 0.0;
         t.width = kMaxTaps + 2;

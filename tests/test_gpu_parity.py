@@ -275,3 +275,60 @@ def test_polynomial_spreading_at_every_density(mm, tile, per_cell):
     ref = oracle_coef(w, N)
     err = series_rel_l2(c, ref)
     assert err[0] <= 1e-6, (n, plan["Mr"], err[0])
+
+
+def _bursty_events(n_base, bursts, seed, dp_dtype=torch.float32):
+    """One series on [0, 1): n_base uniform times plus dense bursts (lo, hi, n) of
+    uniform times, so that one series has sparse tiles, dense tiles and tiles
+    that straddle a burst's edge; bursts at 0 and 1 reach across the periodic wrap."""
+    g = torch.Generator().manual_seed(seed)
+    parts = [torch.rand(n_base, generator=g, dtype=torch.float64)]
+    for lo, hi, n in bursts:
+        parts.append(lo + (hi - lo) * torch.rand(n, generator=g, dtype=torch.float64))
+    t, _ = torch.sort(torch.cat(parts))
+    t = t.clamp(0.0, 1.0)
+    dp = 1e-3 * torch.randn(t.numel(), generator=g, dtype=torch.float64)
+    offs = torch.tensor([0, t.numel()], dtype=torch.int64)
+    return synth.Workload("bursty", offs, t, dp.to(dp_dtype), 0.0, 1.0, 1, 1, [1], seed, {})
+
+
+@pytest.mark.parametrize("per_cell", [0.5, 1.5, 6.4, 20.0])
+@pytest.mark.parametrize("tile", [1024, 2048, 4096])
+def test_moment_and_tap_spreading_against_oracle(mm, per_cell, tile):
+    """Dense tiles spread from per-cell moments (the default from one event per
+    cell), per-event taps everywhere (moment_density -1), and moments for every
+    tile holding an event (moment_density 1e-6): each within tol of the oracle."""
+    N = 2100
+    base = {"spread_direct": 2, "tile": tile}
+    plan = mm.plan_query(N, "es", 1e-6, "mixed", base)
+    n = max(1, int(per_cell * plan["Mr"]))
+    w = synth.random_events(1, n, n, seed=int(per_cell * 10) + tile, dp_dtype=torch.float32)
+    ref = oracle_coef(w, N)
+    for md in (0.0, -1.0, 1e-6):
+        c = gpu_coef(mm, w, N, "es", 1e-6, "mixed", dict(base, moment_density=md))
+        err = series_rel_l2(c, ref)
+        assert err[0] <= 1e-6, (md, n, plan["Mr"], err[0])
+
+
+@pytest.mark.parametrize("kernel", ["es", "kb"])
+@pytest.mark.parametrize("tile", [1024, 2048])
+def test_moments_on_bursty_series_with_wrap(mm, kernel, tile):
+    """A sparse background with bursts of 20-40 events per cell, two of them at
+    the ends of the window (their kernels wrap around the periodic grid): the
+    moment and tap kernels split one series' tiles between them with none left
+    out or taken twice.  Within tol of the oracle, and bit-identical on a rerun."""
+    N = 3000
+    tune = {"spread_direct": 2, "tile": tile}
+    plan = mm.plan_query(N, kernel, 1e-6, "mixed", tune)
+    Mr = plan["Mr"]
+    bursts = [(0.0, 0.004, int(40 * 0.004 * Mr)), (0.31, 0.33, int(20 * 0.02 * Mr)),
+              (0.6, 0.6 + 1000 / Mr, int(30 * 1000)), (0.997, 1.0, int(30 * 0.003 * Mr))]
+    w = _bursty_events(int(0.05 * Mr), bursts, seed=7 + tile)
+    ref = oracle_coef(w, N)
+    c1 = gpu_coef(mm, w, N, kernel, 1e-6, "mixed", tune)
+    c2 = gpu_coef(mm, w, N, kernel, 1e-6, "mixed", tune)
+    assert torch.equal(c1, c2)
+    err = series_rel_l2(c1, ref)
+    assert err[0] <= 1e-6, (kernel, tile, w.t.numel(), err[0])
+    taps = gpu_coef(mm, w, N, kernel, 1e-6, "mixed", dict(tune, moment_density=-1.0))
+    assert series_rel_l2(taps, ref)[0] <= 1e-6
