@@ -63,7 +63,105 @@ def parse():
                          "cross-section timed through mm_estimate")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy (scales FETCH_SIZE/WRITE_SIZE counters)")
+    ap.add_argument("--summarize", nargs="+", metavar=("KIND", "DIR"),
+                    help="print the Markdown table of rocprofv3 CSV output instead of benchmarking: "
+                         "'trace DIR' (kernel durations), 'traffic FETCH_DIR WRITE_DIR COPYF_DIR COPYW_DIR' "
+                         "(HBM bytes per launch, scaled by the copy's counters), 'counters DIR' (per-dispatch "
+                         "medians of every counter)")
     return ap.parse_args()
+
+
+def _short_kernel(name: str) -> str:
+    """mm::k_spread_poly<float, 9, 4>(...) -> k_spread_poly"""
+    n = name.split("(")[0].split("<")[0].split("::")[-1].split()
+    return n[-1] if n else name.strip()
+
+
+def _csvs(d, suffix):
+    import glob
+    return sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True))
+
+
+def _median(v):
+    v = sorted(v)
+    n = len(v)
+    return v[n // 2] if n % 2 else 0.5 * (v[n // 2 - 1] + v[n // 2])
+
+
+def _counter_medians(d):
+    """{kernel: {counter: median over dispatches of the per-dispatch sum}} of a counter_collection CSV."""
+    import csv
+    per = {}
+    for f in _csvs(d, "counter_collection.csv"):
+        for row in csv.DictReader(open(f)):
+            k = _short_kernel(row.get("Kernel_Name", ""))
+            key = (row.get("Counter_Name"), row.get("Dispatch_Id"))
+            per.setdefault(k, {}).setdefault(key, 0.0)
+            per[k][key] += float(row.get("Counter_Value", 0) or 0)
+    out = {}
+    for k, d2 in per.items():
+        byc = {}
+        for (c, _), v in d2.items():
+            byc.setdefault(c, []).append(v)
+        out[k] = {c: (_median(v), len(v)) for c, v in byc.items()}
+    return out
+
+
+def summarize(args):
+    """Markdown tables from rocprofv3 CSV output (the files under profiles/ are made with this)."""
+    import csv
+    kind, dirs = args[0], args[1:]
+    if kind == "trace":
+        durs = {}
+        for f in _csvs(dirs[0], "kernel_trace.csv"):
+            for row in csv.DictReader(open(f)):
+                k = _short_kernel(row.get("Kernel_Name", ""))
+                if not k.startswith("k_"):
+                    continue
+                durs.setdefault(k, []).append((int(row["End_Timestamp"]) - int(row["Start_Timestamp"])) / 1e3)
+        print("| kernel | calls | avg | median | min | max | total |")
+        print("|---|---|---|---|---|---|---|")
+        for k, v in sorted(durs.items(), key=lambda kv: -sum(kv[1])):
+            print("| %s | %d | %.1f | %.1f | %.1f | %.1f | %.1f |" % (k, len(v), sum(v) / len(v), _median(v), min(v),
+                                                                      max(v), sum(v)))
+    elif kind == "traffic":
+        fetch, write, copyf, copyw = (_counter_medians(d) for d in dirs[:4])
+
+        def copy_kib(m, c):
+            vals = [v[c][0] for v in m.values() if c in v]
+            return max(vals) if vals else None
+        cf, cw = copy_kib(copyf, "FETCH_SIZE"), copy_kib(copyw, "WRITE_SIZE")
+        fr, wr = (1 << 20) / cf, (1 << 20) / cw      # bytes a 1 GiB copy moves, per KiB counted
+        print("Calibration: a 1 GiB device-to-device copy reads FETCH_SIZE = %d KiB and WRITE_SIZE = %d KiB, so "
+              "bytes = FETCH_SIZE x 1024 x %.3f and WRITE_SIZE x 1024 x %.3f." % (cf, cw, fr, wr))
+        print()
+        print("source_sha256_16: %s" % source_hash(_tuned_large_universe()))
+        print()
+        print("| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | read MB | written MB | traffic_bytes |")
+        print("|---|---|---|---|---|---|---|")
+        for k in sorted(set(fetch) | set(write)):
+            if not k.startswith("k_"):
+                continue
+            f, n = fetch.get(k, {}).get("FETCH_SIZE", (0.0, 0))
+            w, _ = write.get(k, {}).get("WRITE_SIZE", (0.0, 0))
+            rb, wb = f * 1024 * fr, w * 1024 * wr
+            print("| %s | %d | %.0f | %.0f | %.1f | %.1f | %.0f |" % (k, n, f, w, rb / 1e6, wb / 1e6, rb + wb))
+    elif kind == "counters":
+        m = _counter_medians(dirs[0])
+        cs = sorted({c for v in m.values() for c in v})
+        print("| kernel | " + " | ".join(cs) + " |")
+        print("|---|" + "---|" * len(cs))
+        for k in sorted(m):
+            if k.startswith("k_"):
+                print("| %s | " % k + " | ".join("%.4g" % m[k][c][0] if c in m[k] else "" for c in cs) + " |")
+    else:
+        raise SystemExit("unknown summary kind %r" % kind)
+    return 0
+
+
+def _tuned_large_universe():
+    from paper_2003_02842_amd.tune import LARGE_UNIVERSE, load_tuned
+    return load_tuned("large-universe") or dict(LARGE_UNIVERSE)
 
 
 PROFILE_TRAFFIC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "hbm_traffic.large-universe.md")
@@ -95,11 +193,13 @@ def measured_traffic(kernel: str, tune=None):
     tag = "source_sha256_16: "
     if tag not in text or text.split(tag, 1)[1].split()[0] != source_hash(tune):
         return None
+    parts = kernel.split("+")
+    found = {}
     for line in text.splitlines():
         cells = [c.strip() for c in line.strip().strip("|").split("|")]
-        if cells and cells[0] == kernel and len(cells) >= 7:
-            return float(cells[6])
-    return None
+        if cells and cells[0] in parts and len(cells) >= 7:
+            found[cells[0]] = float(cells[6])
+    return sum(found.values()) if len(found) == len(parts) else None
 
 
 def copy_calibration():
@@ -354,6 +454,8 @@ def pairwise_bench(a):
 
 def main():
     a = parse()
+    if a.summarize:
+        return summarize(a.summarize)
     if a.copy_calibration:
         return copy_calibration()
     if a.gpus != 1:
