@@ -437,7 +437,14 @@ def pairwise_bench(a):
     pair_ms = _best_of(lambda: mm.cov_pairwise(c, 1, D, Ni, a.basis), 3)
     single_ms = _best_of(lambda: mm.cov(c, 1, D, [N], a.basis, ws=ws), 3)
     S, R = mm.cov_pairwise(c, 1, D, Ni, a.basis)
-    del c, ws
+    # an Epps sweep on the same coefficients: 20 log-spaced cutoffs up to N in one
+    # pass over k, beside one product per cutoff
+    Ns = sorted({int(v) for v in np.round(np.geomspace(1, N, 20))})
+    wsw = torch.empty(max(mm.cov_workspace_size(1, D, N, len(Ns), "mixed"), 256), dtype=torch.uint8, device="cuda")
+    sweep_ms = _best_of(lambda: mm.cov(c, 1, D, Ns, a.basis, ws=wsw), 3)
+    separate_ms = sum(_best_of(lambda: mm.cov(c, 1, D, [n], a.basis, ws=ws), 3) for n in Ns)
+    Sw, Rw = mm.cov(c, 1, D, Ns, a.basis, ws=wsw)
+    del c, ws, wsw
     torch.cuda.empty_cache()
     c64 = mm.nufft1(w.offsets, w.t, w.dp.double(), w.t0, w.T, N, a.kernel, 1e-12, "fp64")
     t = time.perf_counter()
@@ -445,11 +452,17 @@ def pairwise_bench(a):
     torch.cuda.synchronize()
     fp64_ms = 1e3 * (time.perf_counter() - t)
     errs = {"cov": _relfro_max(S[None], S64[None]), "corr": _relfro_max(R[None], R64[None])}
-    del c64, S, R, S64, R64
+    del S, R, S64, R64
+    torch.cuda.empty_cache()
+    Sw64, Rw64 = mm.cov(c64, 1, D, Ns, a.basis)
+    sweep_errs = {"cov": _relfro_max(Sw, Sw64), "corr": _relfro_max(Rw, Rw64)}
+    del c64, Sw, Rw, Sw64, Rw64
     torch.cuda.empty_cache()
     return {"ms": pair_ms, "distinct_cutoffs": len(set(Ni)), "cutoff_range": [min(Ni), max(Ni)],
             "single_cutoff_mm_cov_ms": single_ms, "plain_fp64_pairwise_ms": fp64_ms, "rel_err_vs_fp64": errs,
-            "config": "large universe, %d assets each with its own cutoff, %s basis, mixed" % (D, a.basis)}
+            "config": "large universe, %d assets each with its own cutoff, %s basis, mixed" % (D, a.basis),
+            "sweep": {"cutoffs": Ns, "one_pass_ms": sweep_ms, "one_product_per_cutoff_ms": separate_ms,
+                      "rel_err_vs_fp64": sweep_errs}}
 
 
 def main():

@@ -165,6 +165,13 @@ mm_status mm_cov_workspace_size(int32_t G, int32_t D, int32_t Nmax, int32_t nN, 
  *            Sigma_jj <= 0 (an empty series).
  *   tune     NULL, or the contraction's tile and k-split (mm_tuning.syrk_tile, syrk_splits;
  *            the other fields are ignored here)
+ * All cutoffs come from one pass over k where that costs less than a product per
+ * cutoff: small D by FP64 running sums; on the MFMA path (mixed, large D) from
+ * Gram matrices of the k-segments between consecutive cutoffs, summed in k order
+ * (Dirichlet from one product; Fejer from two, the second weighted by N_j - k
+ * within each segment j, so that every cutoff's weights (N - k)/(N(N+1)) come
+ * from non-negative combinations), taken when max(Ns) (twice it for Fejer) is
+ * below the sum of the distinct cutoffs and there are at most 64 of them.
  * Errors: MM_ERR_ARG, MM_ERR_WORKSPACE, MM_ERR_UNSUPPORTED, MM_ERR_HIP. */
 mm_status mm_cov(int32_t G, int32_t D, const void* coef, int64_t ldc, const int32_t* Ns, int32_t nN,
                  mm_basis basis, mm_prec prec, const mm_tuning* tune, void* cov, void* corr, void* ws,

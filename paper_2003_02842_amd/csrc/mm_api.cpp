@@ -128,7 +128,14 @@ static hipError_t enqueue_cov(int32_t G, int32_t D, const void* coef, int64_t ld
         e = launch_cov_small(prec, G, D, coef, ldc, Nmax, cut, basis, cov, st, corr);
         return e;   // the correlations come from the same launch
     } else {
-        for (int q = 0; q < nN && e == hipSuccess; ++q) {
+        // several cutoffs on the MFMA path: one pass over k where that costs less
+        bool done = false;
+        if (prec == MM_MIXED && nN >= 2 && !operands_ready) {
+            e = launch_cov_mfma_sweep(G, D, coef, ldc, Ns, nN, basis, cov, ws, st, sc);
+            done = e == hipSuccess;
+            if (e == hipErrorNotSupported) e = hipSuccess;
+        }
+        for (int q = 0; !done && q < nN && e == hipSuccess; ++q) {
             char* cq = (char*)cov + (size_t)q * G * D * D * es;
             if (prec == MM_MIXED)
                 e = launch_cov_mfma(G, D, coef, ldc, Ns[q], basis, cq, ws, st, operands_ready, sc);
@@ -227,7 +234,7 @@ mm_status mm_cov_workspace_size(int32_t G, int32_t D, int32_t Nmax, int32_t nN, 
     if (!bytes || G < 1 || D < 1 || Nmax < 1 || nN < 1 || nN > kMaxCutoffs) return MM_ERR_ARG;
     if (prec != MM_PLAIN_FP64 && prec != MM_MIXED) return MM_ERR_ARG;
     if (!syrk_choice_ok(tune)) return MM_ERR_ARG;
-    *bytes = (small_d_limit(D) || prec == MM_PLAIN_FP64) ? 0 : cov_mfma_workspace(G, D, Nmax, syrk_choice(tune));
+    *bytes = (small_d_limit(D) || prec == MM_PLAIN_FP64) ? 0 : cov_mfma_workspace(G, D, Nmax, syrk_choice(tune), nN);
     return MM_OK;
 }
 

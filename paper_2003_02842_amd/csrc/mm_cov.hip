@@ -24,6 +24,9 @@
 #include "mm_bf16.h"
 #include "mm_internal.h"
 
+#include <algorithm>
+#include <vector>
+
 namespace mm {
 
 static const double kTwoPi = 6.283185307179586476925286766559;
@@ -299,7 +302,7 @@ __global__ void k_split_bf16(int D, const float2* __restrict__ coef, int64_t ldc
 __global__ __launch_bounds__(256) void k_syrk_mfma(const uint16_t* __restrict__ hi, const uint16_t* __restrict__ lo,
                                                    const uint16_t* __restrict__ bhi, const uint16_t* __restrict__ blo,
                                                    int64_t Kp, int64_t kchunk, int ntiles, int nsplit,
-                                                   float* __restrict__ partial)
+                                                   float* __restrict__ partial, const int32_t* __restrict__ kstep)
 {
     __shared__ __align__(16) uint16_t sAh[ST * SLD];
     __shared__ __align__(16) uint16_t sAl[ST * SLD];
@@ -311,8 +314,9 @@ __global__ __launch_bounds__(256) void k_syrk_mfma(const uint16_t* __restrict__ 
     while (bi * (bi + 1) / 2 > t) --bi;
     while ((bi + 1) * (bi + 2) / 2 <= t) ++bi;
     const int bj = t - bi * (bi + 1) / 2;
-    const int64_t kb = (int64_t)split * kchunk;
-    const int64_t ke = min(kb + kchunk, Kp);
+    // k-range of this split: equal chunks, or (kstep given) k-steps kstep[2 split] .. kstep[2 split + 1]
+    const int64_t kb = kstep ? (int64_t)kstep[2 * split] * SK : (int64_t)split * kchunk;
+    const int64_t ke = kstep ? (int64_t)kstep[2 * split + 1] * SK : min(kb + kchunk, Kp);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wy = wave >> 1, wx = wave & 1;
     const uint16_t* Ah = hi + (int64_t)bi * ST * Kp;
@@ -471,7 +475,8 @@ __global__ __launch_bounds__(256) void k_syrk_mfma256(const uint16_t* __restrict
                                                       const uint16_t* __restrict__ lo,
                                                       const uint16_t* __restrict__ bhi,
                                                       const uint16_t* __restrict__ blo, int64_t Kp, int64_t kchunk,
-                                                      int ntiles, int nsplit, float* __restrict__ partial)
+                                                      int ntiles, int nsplit, float* __restrict__ partial,
+                                                      const int32_t* __restrict__ kstep)
 {
     __shared__ uint4 lds0[4 * T2 * 4];   // [array: A hi, A lo, B hi, B lo][row][chunk], even stages
     __shared__ uint4 lds1[4 * T2 * 4];   // odd stages
@@ -484,8 +489,9 @@ __global__ __launch_bounds__(256) void k_syrk_mfma256(const uint16_t* __restrict
     // a diagonal tile of X X^T (B the same arrays as A) stages one panel and skips
     // its upper quadrant; a product A B^T with B of its own computes every quadrant
     const bool diag = bi == bj && bhi == hi;
-    const int64_t kb = (int64_t)split * kchunk;
-    const int64_t ke = min(kb + kchunk, Kp);
+    // k-range of this split: equal chunks, or (kstep given) k-steps kstep[2 split] .. kstep[2 split + 1]
+    const int64_t kb = kstep ? (int64_t)kstep[2 * split] * SK2 : (int64_t)split * kchunk;
+    const int64_t ke = kstep ? (int64_t)kstep[2 * split + 1] * SK2 : min(kb + kchunk, Kp);
     const int nst = (int)((ke - kb) / SK2);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wy = wave >> 1, wx = wave & 1;
@@ -988,10 +994,341 @@ static MfmaShape mfma_shape(int32_t D, int32_t N, SyrkChoice sc = {})
     return s;
 }
 
-size_t cov_mfma_workspace(int32_t G, int32_t D, int32_t Nmax, SyrkChoice sc)
+// ---------------------------------------------------------------- MFMA N sweep
+// Every cutoff N_1 < ... < N_n of a sweep from one pass over k (Eqs. Der:2/3).
+// The operands hold the k of segment j, (N_{j-1}, N_j], in a column block of its
+// own padded to the product's k-step, and the product's k-ranges never cross a
+// segment, so every partial tile is a Gram matrix of one segment: of X (column
+// scale 2pi sqrt(m_k)) giving G_j = (2pi)^2 sum_{k in j} m_k P_k (P_k = Re c_k^(i)
+// conj c_k^(j)), and for Fejer of Y (2pi sqrt(m_k (N_j - k))) giving
+// H_j = (2pi)^2 sum_{k in j} m_k (N_j - k) P_k.  Then at cutoff N = N_q
+//   Dirichlet  Sigma = sum_{j<=q} G_j / (2N+1),
+//   Fejer      Sigma = sum_{j<=q} ((N - N_j) G_j + H_j) / (N (N+1)),
+// since the Fejer weight (1 - k/N)/(N+1) is (N - k)/(N (N+1)) and N - k =
+// (N - N_j) + (N_j - k).  Every weight is >= 0, so no two separately rounded
+// products are subtracted (a sum of m_k k P_k subtracted from one of m_k P_k
+// cancels where the weights vanish, at small N entirely).  The reduce keeps
+// sum G_j, sum N_j G_j and sum H_j in FP64 over the partials in k order.
+constexpr int kSweepSegs = 64;        // distinct cutoffs of a one-pass sweep
+constexpr int kSweepRanges = 128;     // k-ranges of its product
+constexpr int KS = 32;                // real columns per k-step (SK and SK2)
+
+struct SweepSeg {
+    int n;                            // segments (distinct cutoffs, ascending)
+    int N[kSweepSegs];
+    int32_t cstart[kSweepSegs + 1];   // first column pair of each segment; cstart[n] = Kp / 2
+};
+struct SweepRanges {
+    int nr;
+    int32_t seg[kSweepRanges];        // segment of the r-th range in k order (ascending)
+    int32_t part[kSweepRanges];       // its partial tile set: its place in the product's
+                                      // launch order, which runs the longest ranges first
+};
+struct SweepSteps {
+    int n;                            // entries: (first, end) k-step of each range in launch order
+    int32_t v[2 * kSweepRanges];
+};
+struct SweepSlots {
+    int n;                            // output slots (the caller's cutoffs, in their order)
+    int32_t seg[kMaxCutoffs];         // segment of each slot
+};
+
+struct SweepShape {
+    MfmaShape m;                      // tiles and the model's k-split
+    int64_t Kp;                       // padded columns of the segment layout
+    size_t xhi, xlo, yhi, ylo, p0, p1, kst, tab, total;
+};
+
+// Layout of the sweep's workspace for padded width Kp and nr ranges (bounds for
+// the query: Kp <= the single-cutoff width + KS per cutoff, nr <= the model's
+// split + the cutoffs).
+static SweepShape sweep_shape(int32_t D, int32_t Nmax, int64_t Kp, int nr, int basis, SyrkChoice sc)
+{
+    SweepShape w;
+    w.m = mfma_shape(D, Nmax, sc);
+    w.Kp = Kp;
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t op = al((size_t)w.m.Dp * Kp * 2);
+    const size_t pt = al((size_t)nr * w.m.ntiles * w.m.ts * w.m.ts * 4);
+    const bool fej = basis == MM_FEJER;
+    size_t o = 0;
+    w.xhi = o; o += op;
+    w.xlo = o; o += op;
+    w.yhi = o; o += fej ? op : 0;
+    w.ylo = o; o += fej ? op : 0;
+    w.p0 = o; o += pt;
+    w.p1 = o; o += fej ? pt : 0;
+    w.kst = o; o += al((size_t)2 * nr * 4);
+    w.tab = o; o += al((size_t)Kp / 2 * 16);
+    w.total = o;
+    return w;
+}
+
+size_t cov_mfma_workspace(int32_t G, int32_t D, int32_t Nmax, SyrkChoice sc, int32_t nN)
 {
     (void)G;
-    return mfma_shape(D, Nmax, sc).total;
+    size_t b = mfma_shape(D, Nmax, sc).total;
+    if (nN >= 2) {
+        const MfmaShape m = mfma_shape(D, Nmax, sc);
+        const int n = std::min<int32_t>(nN, kSweepSegs);
+        const int nr = std::min(kSweepRanges, (4 * m.nsplit + n + 7) / 8 * 8);
+        b = std::max(b, sweep_shape(D, Nmax, m.Kp + (int64_t)KS * n, nr, MM_FEJER, sc).total);
+    }
+    return b;
+}
+
+// The column table of the segment layout, once per call: for column pair c its k
+// (-1 in the padding) and the scales of X and Y (FP64, rounded to FP32); block 0
+// also writes the product's k-step pairs.
+__global__ void k_sweep_cols(SweepSeg seg, SweepSteps ks, int64_t kp2, int4* __restrict__ tab,
+                             int32_t* __restrict__ kst)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (blockIdx.x == 0)
+        for (int i = threadIdx.x; i < ks.n; i += blockDim.x) kst[i] = ks.v[i];
+    if (c >= kp2) return;
+    int lo = 0, hi = seg.n;                 // the last segment q with cstart[q] <= c
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (seg.cstart[mid] <= c) lo = mid;
+        else hi = mid;
+    }
+    const int q = lo;
+    const int k = (q == 0 ? 0 : seg.N[q - 1] + 1) + (int)(c - seg.cstart[q]);
+    int4 e = make_int4(-1, 0, 0, 0);
+    if (k <= seg.N[q]) {
+        const double mk = k ? 2.0 : 1.0;
+        e.x = k;
+        e.y = __float_as_int((float)(kTwoPi * sqrt(mk)));
+        e.z = __float_as_int((float)(kTwoPi * sqrt(mk * (double)(seg.N[q] - k))));
+    }
+    tab[c] = e;
+}
+
+// X (and for Fejer Y) of the segment layout as BF16 hi/lo pairs, from the column table.
+__global__ void k_sweep_split(int D, const float2* __restrict__ coef, int64_t ldc, const int4* __restrict__ tab,
+                              int64_t kp2, uint32_t* __restrict__ xhi, uint32_t* __restrict__ xlo,
+                              uint32_t* __restrict__ yhi, uint32_t* __restrict__ ylo)
+{
+    const int64_t row = blockIdx.y;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < kp2; c += (int64_t)gridDim.x * blockDim.x) {
+        const int4 e = tab[c];
+        float2 cc = make_float2(0.f, 0.f);
+        float s0 = 0.f, s1 = 0.f;
+        if (row < D && e.x >= 0) {
+            cc = coef[row * ldc + e.x];
+            s0 = __int_as_float(e.y);
+            s1 = __int_as_float(e.z);
+        }
+        uint32_t h, l;
+        bf16_split_pair(cc.x, cc.y, s0, h, l);
+        xhi[row * kp2 + c] = h;
+        xlo[row * kp2 + c] = l;
+        if (yhi) {
+            bf16_split_pair(cc.x, cc.y, s1, h, l);
+            yhi[row * kp2 + c] = h;
+            ylo[row * kp2 + c] = l;
+        }
+    }
+}
+
+// The reduce of the sweep: the partial tiles of X X^T (p0, the G_j) and Y Y^T (p1,
+// the H_j) added in k order in FP64 as sum G_j, sum N_j G_j and sum H_j, and at
+// the end of each segment Sigma at its cutoff written, mirrored, to every output
+// slot with that cutoff.  Decomposition as k_syrk_reduce.
+template <int TS>
+__global__ __launch_bounds__(256) void k_sweep_reduce(const float* __restrict__ p0, const float* __restrict__ p1,
+                                                      SweepRanges rg, SweepSeg seg, SweepSlots sl, int basis,
+                                                      int ntiles, int D, int G, int g, float* __restrict__ cov)
+{
+    constexpr int QN = TS / 64;
+    constexpr int RB = 16;
+    __shared__ float tileT[RB][65];
+    const int per_tile = QN * QN * (64 / RB);
+    const int t = blockIdx.x / per_tile, rem = blockIdx.x % per_tile;
+    const int quad = rem / (64 / RB), part = rem % (64 / RB);
+    int bi = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while (bi * (bi + 1) / 2 > t) --bi;
+    while ((bi + 1) * (bi + 2) / 2 <= t) ++bi;
+    const int bj = t - bi * (bi + 1) / 2;
+    const int qi = (quad / QN) * 64, qj = (quad % QN) * 64;
+    if (bi == bj && qi < qj) return;   // mirrored from below
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int64_t tstride = (int64_t)ntiles * TS * TS;
+    const int64_t DD = (int64_t)D * D;
+    double sg[RB / 4], sng[RB / 4], sh[RB / 4];   // sum G_j, sum N_j G_j, sum H_j
+#pragma unroll
+    for (int u = 0; u < RB / 4; ++u) sg[u] = sng[u] = sh[u] = 0.0;
+    for (int r = 0; r < rg.nr; ++r) {
+        const double Nj = (double)seg.N[rg.seg[r]];
+#pragma unroll
+        for (int u = 0; u < RB / 4; ++u) {
+            const int li = qi + part * RB + ty + 4 * u, lj = qj + tx;
+            const int64_t at = rg.part[r] * tstride + (int64_t)t * TS * TS + li * TS + lj;
+            const double gv = (double)p0[at];
+            sg[u] += gv;
+            sng[u] += Nj * gv;
+            if (p1) sh[u] += (double)p1[at];
+        }
+        if (r + 1 < rg.nr && rg.seg[r + 1] == rg.seg[r]) continue;   // uniform: the segment goes on
+        const int q = rg.seg[r];
+        const double Nd = (double)seg.N[q];
+        float v[RB / 4];
+#pragma unroll
+        for (int u = 0; u < RB / 4; ++u)
+            v[u] = (float)(basis == MM_DIRICHLET ? sg[u] / (2.0 * Nd + 1.0)
+                                                 : (Nd * sg[u] - sng[u] + sh[u]) / (Nd * (Nd + 1.0)));
+        for (int sidx = 0; sidx < sl.n; ++sidx) {
+            if (sl.seg[sidx] != q) continue;   // uniform
+            float* C = cov + ((int64_t)sidx * G + g) * DD;
+#pragma unroll
+            for (int u = 0; u < RB / 4; ++u) {
+                const int lr = ty + 4 * u;
+                const int i = bi * TS + qi + part * RB + lr, j = bj * TS + qj + tx;
+                if (bi == bj) {
+                    // diagonal tile: both entries from the lower one, so Sigma is exactly symmetric
+                    if (i < D && j <= i) {
+                        C[(int64_t)i * D + j] = v[u];
+                        C[(int64_t)j * D + i] = v[u];
+                    }
+                } else {
+                    if (i < D && j < D) C[(int64_t)i * D + j] = v[u];
+                    tileT[lr][tx] = v[u];
+                }
+            }
+            if (bi == bj) continue;
+            __syncthreads();
+            for (int e = threadIdx.x; e < 64 * RB; e += 256) {
+                const int c = e / RB, lr = e % RB;
+                const int j = bj * TS + qj + c, i = bi * TS + qi + part * RB + lr;
+                if (i < D && j < D) C[(int64_t)j * D + i] = tileT[lr][c];
+            }
+            __syncthreads();
+        }
+    }
+}
+
+hipError_t launch_cov_mfma_sweep(int32_t G, int32_t D, const void* coef, int64_t ldc, const int32_t* Ns, int32_t nN,
+                                 int basis, void* cov, char* ws, hipStream_t st, SyrkChoice sc)
+{
+    // distinct cutoffs, ascending
+    std::vector<int> u(Ns, Ns + nN);
+    std::sort(u.begin(), u.end());
+    u.erase(std::unique(u.begin(), u.end()), u.end());
+    const int n = (int)u.size();
+    if (n < 2 || n > kSweepSegs) return hipErrorNotSupported;
+    // one pass costs one product over max N (two for Fejer); separate products cost
+    // the sum of the cutoffs
+    double sumN = 0.0;
+    for (int v : u) sumN += (double)v + 1.0;
+    if ((basis == MM_FEJER ? 2.0 : 1.0) * ((double)u.back() + 1.0) >= sumN) return hipErrorNotSupported;
+    const int Nmax = u.back();
+    const MfmaShape m = mfma_shape(D, Nmax, sc);
+    SweepSeg seg;
+    seg.n = n;
+    int64_t steps = 0;
+    std::vector<int64_t> seg_steps(n);
+    for (int q = 0; q < n; ++q) {
+        seg.N[q] = u[q];
+        seg.cstart[q] = (int32_t)(steps * KS / 2);
+        const int64_t cols = 2ll * (u[q] - (q ? u[q - 1] : -1));
+        seg_steps[q] = (cols + KS - 1) / KS;
+        steps += seg_steps[q];
+    }
+    seg.cstart[n] = (int32_t)(steps * KS / 2);
+    const int64_t Kp = steps * KS;
+    // k-ranges: each segment cut into pieces of at most about steps / (2 nsplit)
+    // k-steps (half the model's single-cutoff ranges, so that the uneven pieces pack
+    // evenly onto the CUs); the reduce reads them in k order
+    const int64_t Lr = std::max<int64_t>(1, (steps + 4 * m.nsplit - 1) / (4 * m.nsplit));
+    std::vector<int64_t> rb, re;
+    std::vector<int> rq;
+    int64_t at = 0;
+    for (int q = 0; q < n; ++q) {
+        const int64_t pieces = (seg_steps[q] + Lr - 1) / Lr;
+        for (int64_t p = 0; p < pieces; ++p) {
+            rb.push_back(at + seg_steps[q] * p / pieces);
+            re.push_back(at + seg_steps[q] * (p + 1) / pieces);
+            rq.push_back(q);
+        }
+        at += seg_steps[q];
+    }
+    const int nk = (int)rb.size();                 // ranges in k order
+    const int nr = (nk + 7) / 8 * 8;               // launched: padded with empty ranges
+    if (nr > kSweepRanges) return hipErrorNotSupported;
+    // The product hands each XCD a contiguous eighth of its (range, tile) sequence:
+    // the ranges are dealt longest first, snake-wise, into eight groups of nr/8 (equal
+    // counts, near-equal k), each group in descending length, the groups in turn.
+    std::vector<int> order(nk);
+    for (int r = 0; r < nk; ++r) order[r] = r;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return re[x] - rb[x] > re[y] - rb[y]; });
+    std::vector<std::vector<int>> grp(8);
+    for (int i = 0; i < nr; ++i) {
+        const int round = i / 8, pos = i % 8;
+        grp[round & 1 ? 7 - pos : pos].push_back(i < nk ? order[i] : -1);
+    }
+    SweepRanges rg;
+    SweepSteps ks;
+    rg.nr = nk;
+    ks.n = 2 * nr;
+    int s2 = 0;
+    for (int x = 0; x < 8; ++x)
+        for (int r : grp[x]) {
+            ks.v[2 * s2] = r < 0 ? 0 : (int32_t)rb[r];
+            ks.v[2 * s2 + 1] = r < 0 ? 0 : (int32_t)re[r];
+            if (r >= 0) rg.part[r] = s2;
+            ++s2;
+        }
+    for (int r = 0; r < nk; ++r) rg.seg[r] = rq[r];
+    SweepSlots sl;
+    sl.n = nN;
+    for (int i = 0; i < nN; ++i) sl.seg[i] = (int32_t)(std::lower_bound(u.begin(), u.end(), Ns[i]) - u.begin());
+    const SweepShape w = sweep_shape(D, Nmax, Kp, nr, basis, sc);
+    if (w.total > cov_mfma_workspace(G, D, Nmax, sc, nN)) return hipErrorNotSupported;   // outside the queried bound
+    const bool fej = basis == MM_FEJER;
+    uint16_t* xhi = (uint16_t*)(ws + w.xhi);
+    uint16_t* xlo = (uint16_t*)(ws + w.xlo);
+    uint16_t* yhi = fej ? (uint16_t*)(ws + w.yhi) : nullptr;
+    uint16_t* ylo = fej ? (uint16_t*)(ws + w.ylo) : nullptr;
+    float* p0 = (float*)(ws + w.p0);
+    float* p1 = fej ? (float*)(ws + w.p1) : nullptr;
+    int32_t* kst = (int32_t*)(ws + w.kst);
+    int4* tab = (int4*)(ws + w.tab);
+    prof_begin("k_sweep_cols", st);
+    hipLaunchKernelGGL(k_sweep_cols, dim3((unsigned)((Kp / 2 + 255) / 256)), dim3(256), 0, st, seg, ks, Kp / 2, tab,
+                       kst);
+    prof_end("k_sweep_cols", st);
+    for (int g = 0; g < G; ++g) {
+        const float2* cg = (const float2*)coef + (int64_t)g * D * ldc;
+        const int bx = (int)std::min<int64_t>((Kp / 2 + 255) / 256, 64);
+        prof_begin("k_sweep_split", st);
+        hipLaunchKernelGGL(k_sweep_split, dim3(bx, m.Dp), dim3(256), 0, st, D, cg, ldc, (const int4*)tab, Kp / 2,
+                           (uint32_t*)xhi, (uint32_t*)xlo, (uint32_t*)yhi, (uint32_t*)ylo);
+        prof_end("k_sweep_split", st);
+        const char* name = m.ts == T2 ? "k_syrk_mfma256" : "k_syrk_mfma";
+        for (int pass = 0; pass < (fej ? 2 : 1); ++pass) {
+            const uint16_t* ah = pass ? yhi : xhi;
+            const uint16_t* al = pass ? ylo : xlo;
+            float* pp = pass ? p1 : p0;
+            prof_begin(name, st);
+            if (m.ts == T2)
+                hipLaunchKernelGGL(k_syrk_mfma256, dim3((unsigned)(m.ntiles * nr)), dim3(256), 0, st, ah, al, ah, al,
+                                   Kp, (int64_t)0, m.ntiles, nr, pp, (const int32_t*)kst);
+            else
+                hipLaunchKernelGGL(k_syrk_mfma, dim3((unsigned)(m.ntiles * nr)), dim3(256), 0, st, ah, al, ah, al,
+                                   Kp, (int64_t)0, m.ntiles, nr, pp, (const int32_t*)kst);
+            prof_end(name, st);
+        }
+        prof_begin("k_sweep_reduce", st);
+        if (m.ts == T2)
+            hipLaunchKernelGGL(k_sweep_reduce<T2>, dim3((unsigned)(64 * m.ntiles)), dim3(256), 0, st, p0, p1, rg, seg,
+                               sl, basis, m.ntiles, D, G, g, (float*)cov);
+        else
+            hipLaunchKernelGGL(k_sweep_reduce<ST>, dim3((unsigned)(16 * m.ntiles)), dim3(256), 0, st, p0, p1, rg, seg,
+                               sl, basis, m.ntiles, D, G, g, (float*)cov);
+        prof_end("k_sweep_reduce", st);
+    }
+    return hipGetLastError();
 }
 
 // Zero padding of the split operands when the row pass writes them: the pairs
@@ -1093,10 +1430,10 @@ hipError_t launch_cov_pair(int prec, int32_t G, int32_t D, const void* coef, int
             prof_begin(name, st);
             if (m.ts == T2)
                 hipLaunchKernelGGL(k_syrk_mfma256, dim3((unsigned)(m.ntiles * m.nsplit)), dim3(256), 0, st, ahi, alo,
-                                   bhi, blo, m.Kp, m.kchunk, m.ntiles, m.nsplit, part);
+                                   bhi, blo, m.Kp, m.kchunk, m.ntiles, m.nsplit, part, (const int32_t*)nullptr);
             else
                 hipLaunchKernelGGL(k_syrk_mfma, dim3((unsigned)(m.ntiles * m.nsplit)), dim3(256), 0, st, ahi, alo,
-                                   bhi, blo, m.Kp, m.kchunk, m.ntiles, m.nsplit, part);
+                                   bhi, blo, m.Kp, m.kchunk, m.ntiles, m.nsplit, part, (const int32_t*)nullptr);
             prof_end(name, st);
             prof_begin("k_syrk_reduce", st);
             if (m.ts == T2)
@@ -1166,10 +1503,10 @@ hipError_t launch_cov_mfma(int32_t G, int32_t D, const void* coef, int64_t ldc, 
         prof_begin(syrk_name, st);
         if (s.ts == T2)
             hipLaunchKernelGGL(k_syrk_mfma256, dim3((unsigned)(s.ntiles * s.nsplit)), dim3(256), 0, st, hi, lo, hi, lo,
-                               s.Kp, s.kchunk, s.ntiles, s.nsplit, part);
+                               s.Kp, s.kchunk, s.ntiles, s.nsplit, part, (const int32_t*)nullptr);
         else
             hipLaunchKernelGGL(k_syrk_mfma, dim3((unsigned)(s.ntiles * s.nsplit)), dim3(256), 0, st, hi, lo, hi, lo,
-                               s.Kp, s.kchunk, s.ntiles, s.nsplit, part);
+                               s.Kp, s.kchunk, s.ntiles, s.nsplit, part, (const int32_t*)nullptr);
         prof_end(syrk_name, st);
         prof_begin("k_syrk_reduce", st);
         if (s.ts == T2)

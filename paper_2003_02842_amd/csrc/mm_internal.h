@@ -219,7 +219,13 @@ struct Cutoffs {
 hipError_t launch_cov_small(int prec, int32_t G, int32_t D, const void* coef, int64_t ldc, int32_t Nmax,
                             const Cutoffs& cut, int basis, void* cov, hipStream_t st, void* corr = nullptr);
 hipError_t launch_corr(int prec, int64_t mats, int32_t D, const void* cov, void* corr, hipStream_t st);
-size_t cov_mfma_workspace(int32_t G, int32_t D, int32_t Nmax, SyrkChoice sc = {});
+// (with nN >= 2, also enough for the one-pass sweep of nN cutoffs)
+size_t cov_mfma_workspace(int32_t G, int32_t D, int32_t Nmax, SyrkChoice sc = {}, int32_t nN = 1);
+// The MFMA contraction of nN >= 2 cutoffs in one pass over k (segment Gram
+// matrices, summed in k order): hipErrorNotSupported where the cutoffs exceed its
+// tables or where separate products per cutoff cost less (the caller runs those).
+hipError_t launch_cov_mfma_sweep(int32_t G, int32_t D, const void* coef, int64_t ldc, const int32_t* Ns, int32_t nN,
+                                 int basis, void* cov, char* ws, hipStream_t st, SyrkChoice sc = {});
 hipError_t launch_pairwise_select(int prec, int32_t G, int32_t D, const int32_t* qidx, const void* sweep, void* cov,
                                   void* corr, hipStream_t st);
 // operands_ready: the split operands were written by the NUFFT's row pass

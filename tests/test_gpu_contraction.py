@@ -97,3 +97,43 @@ def test_small_d_sweep_matches_oracle(mm, D, prec):
             for g in range(G):
                 assert relfro(S[q, g], So[q, g]) <= bar, (D, Ns[q], g)
                 assert relfro(R[q, g], Ro[q, g]) <= bar, (D, Ns[q], g)
+
+
+@pytest.mark.parametrize("D,N", [(300, 1500), (2100, 600)])
+@pytest.mark.parametrize("basis,b", [("dirichlet", oracle.DIRICHLET), ("fejer", oracle.FEJER)])
+def test_mfma_sweep_in_one_pass(mm, D, N, basis, b):
+    """A sweep of cutoffs on the MFMA path (both tile kernels) in one pass over k:
+    segment Gram matrices summed in k order, Sigma read off at each cutoff.  The
+    cutoffs come unsorted and with a repeat; every slot against the oracle, and the
+    one-pass kernels are the ones that ran."""
+    c = random_coefficients(D, N, seed=7 * D + N)
+    Ns = [N, 1, 2, 3, 5, 8, 13, 21, 34, 55, 89, 144, 233, 377, 5, N // 2, N - 1]
+    mm.profile_reset()
+    mm.profile_enable(True)
+    S, R = mm.cov(torch.from_numpy(c).cuda(), 1, D, Ns, basis)
+    torch.cuda.synchronize()
+    mm.profile_enable(False)
+    assert mm.profile_read("k_sweep_reduce")[1] == 1
+    So, Ro = oracle.cov(c.astype(np.complex128), 1, D, Ns, b)
+    S, R = S.cpu().numpy(), R.cpu().numpy()
+    for q in range(len(Ns)):
+        assert relfro(S[q, 0], So[q, 0]) <= 1e-5, (D, Ns[q], relfro(S[q, 0], So[q, 0]))
+        assert relfro(R[q, 0], Ro[q, 0]) <= 1e-5, (D, Ns[q], relfro(R[q, 0], Ro[q, 0]))
+        assert np.array_equal(S[q, 0], S[q, 0].T)
+    assert np.array_equal(S[4, 0], S[14, 0])      # the repeated cutoff
+
+
+def test_mfma_sweep_declined_when_separate_products_cost_less(mm):
+    """Two Fejer cutoffs (N/2, N) cost less as two products than as the one-pass
+    sweep's two full-width products: the per-cutoff path runs, within the bar."""
+    D, N = 300, 1200
+    c = random_coefficients(D, N, seed=12)
+    mm.profile_reset()
+    mm.profile_enable(True)
+    S, R = mm.cov(torch.from_numpy(c).cuda(), 1, D, [N // 2, N], "fejer")
+    torch.cuda.synchronize()
+    mm.profile_enable(False)
+    assert mm.profile_read("k_sweep_reduce")[1] == 0
+    So, Ro = oracle.cov(c.astype(np.complex128), 1, D, [N // 2, N], oracle.FEJER)
+    for q in range(2):
+        assert relfro(S[q, 0].cpu().numpy(), So[q, 0]) <= 1e-5
