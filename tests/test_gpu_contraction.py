@@ -137,3 +137,18 @@ def test_mfma_sweep_declined_when_separate_products_cost_less(mm):
     So, Ro = oracle.cov(c.astype(np.complex128), 1, D, [N // 2, N], oracle.FEJER)
     for q in range(2):
         assert relfro(S[q, 0].cpu().numpy(), So[q, 0]) <= 1e-5
+
+
+def test_mfma_sweep_groups(mm):
+    """The one-pass sweep over two groups of D = 300: each group's slots against
+    the oracle (the group offset of the outputs and of the operands)."""
+    D, N, G = 300, 900, 2
+    c = np.concatenate([random_coefficients(D, N, seed=31), random_coefficients(D, N, seed=32)])
+    Ns = [1, 3, 9, 27, 81, 243, 729, 900]
+    S, R = mm.cov(torch.from_numpy(c).cuda(), G, D, Ns, "fejer")
+    So, Ro = oracle.cov(c.astype(np.complex128), G, D, Ns, oracle.FEJER)
+    S, R = S.cpu().numpy(), R.cpu().numpy()
+    for q in range(len(Ns)):
+        for g in range(G):
+            assert relfro(S[q, g], So[q, g]) <= 1e-5, (q, g)
+            assert relfro(R[q, g], Ro[q, g]) <= 1e-5, (q, g)

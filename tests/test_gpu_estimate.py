@@ -61,12 +61,20 @@ def test_estimate_equals_two_calls_and_oracle(mm, basis, prec, tol):
             assert relfro(R2[q, g].cpu().numpy(), Ro[q, 0]) <= bar
 
 
-@pytest.mark.parametrize("case", ["replicates-mixed", "replicates-fp64", "wide-mfma"])
+@pytest.mark.parametrize("case", ["replicates-mixed", "replicates-fp64", "wide-mfma", "mfma-sweep", "dense-moments"])
 def test_graph_replays_match_eager(mm, case):
     if case == "wide-mfma":
         # D = 60 (1830 pairs) takes the split-BF16 MFMA contraction
         w = synth.random_events(60, 0, 3000, seed=11, T=28_800.0, dp_dtype=torch.float32, device="cuda")
         G, D, Ns, prec, tol = 1, 60, [7, 900], "mixed", 1e-6
+    elif case == "mfma-sweep":
+        # two groups of 60 and eleven cutoffs: the one-pass sweep on the MFMA path
+        w = synth.random_events(120, 0, 3000, seed=13, T=28_800.0, dp_dtype=torch.float32, device="cuda")
+        G, D, Ns, prec, tol = 2, 60, [900, 1, 2, 4, 8, 16, 32, 64, 128, 256, 512], "mixed", 1e-6
+    elif case == "dense-moments":
+        # about 5 events per grid cell: the dense tiles spread from per-cell moments
+        w = synth.random_events(40, 20_000, 22_000, seed=17, T=28_800.0, dp_dtype=torch.float32, device="cuda")
+        G, D, Ns, prec, tol = 1, 40, [1000], "mixed", 1e-6
     else:
         prec = "mixed" if case.endswith("mixed") else "fp64"
         w = replicates(8, prec)
@@ -92,6 +100,14 @@ def test_graph_replays_match_eager(mm, case):
         S_e, R_e, _ = mm.estimate(w.offsets, w.t, w.dp, w.t0, w.T, G, D, Ns, "fejer", "es", tol, prec)
         torch.cuda.synchronize()
         assert same(got[0], S_e) and same(got[1], R_e), (case, rep)
+        if rep == 0 and case in ("mfma-sweep", "dense-moments"):
+            # the path the case is there for is the one that ran
+            mm.profile_reset()
+            mm.profile_enable(True)
+            mm.estimate(w.offsets, w.t, w.dp, w.t0, w.T, G, D, Ns, "fejer", "es", tol, prec)
+            torch.cuda.synchronize()
+            mm.profile_enable(False)
+            assert mm.profile_read("k_sweep_reduce" if case == "mfma-sweep" else "k_spread_mom")[1] >= 1
     # the default stream path (side stream inside the binding) replays the same way
     S_d, R_d, _ = mm.estimate(w.offsets, w.t, w.dp, w.t0, w.T, G, D, Ns, "fejer", "es", tol, prec, use_graph=True,
                               out=out, ws=ws)
