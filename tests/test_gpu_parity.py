@@ -332,3 +332,20 @@ def test_moments_on_bursty_series_with_wrap(mm, kernel, tile):
     assert err[0] <= 1e-6, (kernel, tile, w.t.numel(), err[0])
     taps = gpu_coef(mm, w, N, kernel, 1e-6, "mixed", dict(tune, moment_density=-1.0))
     assert series_rel_l2(taps, ref)[0] <= 1e-6
+
+
+@pytest.mark.parametrize("kernel,tol", [("es", 1e-4), ("kb", 1e-4), ("es", 1e-3), ("kb", 1e-5)])
+def test_moments_at_narrower_widths(mm, kernel, tol):
+    """Dense series (6 events per cell) at looser tolerances: narrower kernels and
+    lower polynomial degrees through the moment kernel, against the oracle at tol,
+    beside the tap kernel on the same data."""
+    N = 1500
+    tune = {"spread_direct": 2, "tile": 2048}
+    plan = mm.plan_query(N, kernel, tol, "mixed", tune)
+    n = int(6 * plan["Mr"])
+    w = synth.random_events(2, n, n, seed=int(-np.log10(tol)) * 10 + len(kernel), dp_dtype=torch.float32)
+    ref = oracle_coef(w, N)
+    for md in (0.0, -1.0):
+        c = gpu_coef(mm, w, N, kernel, tol, "mixed", dict(tune, moment_density=md))
+        err = series_rel_l2(c, ref)
+        assert max(err) <= tol, (kernel, tol, plan["width"], md, err)
