@@ -192,8 +192,11 @@ mm_status mm_estimate_workspace_size(int32_t G, int32_t D, const int32_t* Ns, in
  *            them in ws.  With NULL, G = 1, one cutoff and D on the MFMA path (mixed,
  *            D(D+1)/2 > 1024, two-pass FFT), the coefficients are not stored at all:
  *            the FFT's row pass writes the contraction's split BF16 operands itself,
- *            rounded exactly as the split step would, so the results equal the
- *            two-call form bit for bit.
+ *            one FFT row (fixed k1, coefficients k1 + L1 k2) per contiguous run of
+ *            columns.  The contraction sums the same kind of products in another
+ *            column order, so the results agree with the two-call form to FP32
+ *            summation rounding, not bit for bit; repeated calls and graph replays
+ *            are bit for bit.
  *   cov, corr  as mm_cov (corr may be NULL).
  *   ws       device workspace of at least mm_estimate_workspace_size bytes (256-byte aligned).
  *   use_graph 1: the first call with a given set of arguments (every pointer, size,

@@ -98,7 +98,7 @@ static hipError_t enqueue_nufft(const Plan& p, const NufftWs& w, char* wsb, int3
         const bool one_pass = fz || S <= w.S_grid;
         const RangeReq rr{offsets, t, 0, S, fz ? 1 : (p.Mr + kRangeCells - 1) / kRangeCells,
                           fz ? kFusedMaxCells : kRangeCells, t0, T, (int64_t*)(wsb + w.ranges)};
-        hipError_t e = launch_prep(p, w, wsb, st, one_pass ? &rr : nullptr);
+        hipError_t e = launch_prep(p, w, wsb, st, one_pass ? &rr : nullptr, so);
         if (e != hipSuccess) return e;
         if (fz) return launch_nufft_fused(p, w, wsb, S, t, dp, dp_is_fp64, t0, T, coef, ldc, st);
         return launch_nufft_tiled(p, w, wsb, 0, S, offsets, t, dp, dp_is_fp64, t0, T, coef, ldc, st, so, one_pass);
@@ -275,7 +275,11 @@ EstLayout est_layout(const Plan& p, int32_t S, int32_t G, int32_t D, int32_t Nma
     EstLayout L;
     const size_t cs = p.prec == MM_MIXED ? 8 : 16;
     size_t cw = 0;
-    mm_cov_workspace_size(G, D, Nmax, nN, (mm_prec)p.prec, tune, &cw);
+    // room for the operands of the split fused into the row pass (one group, one
+    // cutoff): L1 ceil((N+1)/L1) columns
+    const int32_t Ncov = (G == 1 && nN == 1 && p.prec == MM_MIXED && p.fft_ab)
+                             ? std::max(Nmax, split_out_cols(Nmax, p.L1) - 1) : Nmax;
+    mm_cov_workspace_size(G, D, Ncov, nN, (mm_prec)p.prec, tune, &cw);
     L.coef = 0;
     L.nufft = al256((size_t)S * (size_t)(Nmax + 1) * cs);
     L.cov = L.nufft + al256(nufft_workspace(p, S).total);
@@ -355,17 +359,20 @@ mm_status mm_estimate(int32_t G, int32_t D, const int64_t* offsets, const double
     // values, rounded the same way, as the split step would).
     const bool fuse = !coef_out && G == 1 && nN == 1 && prec == MM_MIXED && !use_fused(p, S) && p.fft_ab &&
                       !small_d_limit(D);
-    const SplitOut so = fuse ? cov_mfma_split_out(D, Ns[0], wsb + L.cov, sc) : SplitOut{nullptr, nullptr, 0, nullptr};
+    const SplitOut so = fuse ? cov_mfma_split_out(D, Ns[0], p.L1, wsb + L.cov, sc) : SplitOut{};
+    // the contraction then runs on its operands' L1 K2 columns (zero beyond N)
+    const int32_t Nop = fuse ? split_out_cols(Ns[0], p.L1) - 1 : Nmax;
     auto enqueue = [&]() -> hipError_t {
         hipError_t e = hipSuccess;
         if (fuse) {
-            e = launch_split_prologue(D, Ns[0], basis, wsb + L.cov, st, sc);
+            e = launch_split_prologue(D, Ns[0], p.L1, basis, wsb + L.cov, st, sc);
             if (e != hipSuccess) return e;
         }
         e = enqueue_nufft(p, w, wsb + L.nufft, S, offsets, t, dp, dp_is_fp64, t0, T, coef, ldc, st,
                           fuse ? &so : nullptr);
         if (e != hipSuccess) return e;
-        return enqueue_cov(G, D, coef, ldc, Ns, nN, Nmax, basis, prec, cov, corr, wsb + L.cov, st, fuse, sc);
+        return enqueue_cov(G, D, coef, ldc, fuse ? &Nop : Ns, nN, fuse ? Nop : Nmax, basis, prec, cov, corr,
+                           wsb + L.cov, st, fuse, sc);
     };
     if (!use_graph) return hip_status(enqueue());
 

@@ -911,7 +911,7 @@ struct MfmaShape {
     int ts;               // tile edge: 128 or 256
     int tn, ntiles, nsplit;
     int64_t Dp, Kp, kchunk;
-    size_t hi, lo, partial, scale, total;
+    size_t hi, lo, partial, scale, fac, total;
 };
 
 // k-ranges per 256-wide tile: the workgroups (tiles x ranges) run in rounds of 256
@@ -966,6 +966,7 @@ static MfmaShape mfma_shape(int32_t D, int32_t N, SyrkChoice sc = {})
         s.lo = o; o += al((size_t)s.Dp * s.Kp * 2);
         s.partial = o; o += al((size_t)s.nsplit * s.ntiles * T2 * T2 * 4);
         s.scale = o; o += al((size_t)s.Kp / 2 * 4);
+        s.fac = o; o += al((size_t)s.Kp / 2 * 4);
         s.total = o;
         return s;
     }
@@ -990,6 +991,7 @@ static MfmaShape mfma_shape(int32_t D, int32_t N, SyrkChoice sc = {})
     s.lo = o; o += al((size_t)s.Dp * s.Kp * 2);
     s.partial = o; o += al((size_t)s.nsplit * s.ntiles * ST * ST * 4);
     s.scale = o; o += al((size_t)s.Kp / 2 * 4);
+    s.fac = o; o += al((size_t)s.Kp / 2 * 4);
     s.total = o;
     return s;
 }
@@ -1332,43 +1334,51 @@ hipError_t launch_cov_mfma_sweep(int32_t G, int32_t D, const void* coef, int64_t
 }
 
 // Zero padding of the split operands when the row pass writes them: the pairs
-// beyond N of rows below D (tail = kp2 - N - 1 each), then rows D..Dp-1 whole,
-// as one grid-stride range.
-__global__ void k_split_pad(int D, int Dp, int N, int64_t kp2, uint32_t* __restrict__ hi, uint32_t* __restrict__ lo)
+// from column ncol on of rows below D (tail = kp2 - ncol each), then rows
+// D..Dp-1 whole, as one grid-stride range.
+__global__ void k_split_pad(int D, int Dp, int64_t ncol, int64_t kp2, uint32_t* __restrict__ hi,
+                            uint32_t* __restrict__ lo)
 {
-    const int64_t tail = kp2 - N - 1;
+    const int64_t tail = kp2 - ncol;
     const int64_t n1 = (int64_t)D * tail, total = n1 + (int64_t)(Dp - D) * kp2;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t at = i < n1 ? (i / tail) * kp2 + (N + 1) + i % tail : (int64_t)D * kp2 + (i - n1);
+        const int64_t at = i < n1 ? (i / tail) * kp2 + ncol + i % tail : (int64_t)D * kp2 + (i - n1);
         hi[at] = 0u;
         lo[at] = 0u;
     }
 }
 
-SplitOut cov_mfma_split_out(int32_t D, int32_t N, char* ws, SyrkChoice sc)
+int32_t split_out_cols(int32_t N, int32_t L1) { return L1 * ((N + L1) / L1); }
+
+SplitOut cov_mfma_split_out(int32_t D, int32_t N, int32_t L1, char* ws, SyrkChoice sc)
 {
-    const MfmaShape s = mfma_shape(D, N, sc);
+    const int32_t ncol = split_out_cols(N, L1);
+    const MfmaShape s = mfma_shape(D, ncol - 1, sc);
     SplitOut o;
     o.hi = (uint32_t*)(ws + s.hi);
     o.lo = (uint32_t*)(ws + s.lo);
     o.kp2 = s.Kp / 2;
+    o.k2n = ncol / L1;
     o.scale = (const float*)(ws + s.scale);
+    o.fac = (float*)(ws + s.fac);
     return o;
 }
 
-hipError_t launch_split_prologue(int32_t D, int32_t N, int basis, char* ws, hipStream_t st, SyrkChoice sc)
+hipError_t launch_split_prologue(int32_t D, int32_t N, int32_t L1, int basis, char* ws, hipStream_t st,
+                                 SyrkChoice sc)
 {
-    const MfmaShape s = mfma_shape(D, N, sc);
+    const int32_t ncol = split_out_cols(N, L1);
+    const MfmaShape s = mfma_shape(D, ncol - 1, sc);
     prof_begin("k_split_scale", st);
     hipLaunchKernelGGL(k_split_scale, dim3((unsigned)((s.Kp / 2 + 255) / 256)), dim3(256), 0, st, N, basis, s.Kp / 2,
                        (float*)(ws + s.scale));
     prof_end("k_split_scale", st);
     const int64_t kp2 = s.Kp / 2;
-    const int64_t total = (int64_t)D * (kp2 - N - 1) + (s.Dp - D) * kp2;
+    const int64_t total = (int64_t)D * (kp2 - ncol) + (s.Dp - D) * kp2;
     const int bx = (int)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 1024));
     prof_begin("k_split_pad", st);
-    hipLaunchKernelGGL(k_split_pad, dim3(bx), dim3(256), 0, st, D, (int)s.Dp, N, kp2, (uint32_t*)(ws + s.hi),
-                       (uint32_t*)(ws + s.lo));
+    hipLaunchKernelGGL(k_split_pad, dim3(bx), dim3(256), 0, st, D, (int)s.Dp, (int64_t)ncol, kp2,
+                       (uint32_t*)(ws + s.hi), (uint32_t*)(ws + s.lo));
     prof_end("k_split_pad", st);
     return hipGetLastError();
 }

@@ -15,7 +15,9 @@
 //                  twiddle W_L^{k1 l2}, in place
 //   k_fft_rows_ab  length-L2 transforms of the row pairs (k1, L1 - k1), the
 //                  real-input untangling, deconvolution (Eq. Der:17) and the 1/2pi
-//                  of the coefficient definition; writes c_k, k = 0..N
+//                  of the coefficient definition; writes c_k, k = 0..N, or (the
+//                  split step fused) the contraction's BF16 operands, one
+//                  contiguous run per row
 //
 // Long twiddle tables are split in two, W^m = lo[m mod LO] hi[m / LO], so both
 // halves (about 2 sqrt(L) entries) sit in LDS.
@@ -155,6 +157,43 @@ __global__ __launch_bounds__(512) void k_fft_rows_ab(const T* __restrict__ grid,
         }
     }
     __syncthreads();
+    // X_k for rows k1 and columns k2 (Zk: row k1, column k2; Zm: the mirror value)
+    auto untangle = [&](int i, int side, int k1, int k2, int k, C& A, C& WB) {
+        const int k2m = (k1 == 0) ? (k2 == 0 ? 0 : L2 - k2) : (L2 - 1 - k2);
+        const C Zk = sh[(2 * i + side) * rs + k2];
+        const C Zm = sh[(2 * i + 1 - side) * rs + k2m];
+        A = C{Zk.x + Zm.x, Zk.y - Zm.y};
+        const C Bv = C{Zk.x - Zm.x, Zk.y + Zm.y};
+        WB = cmulf(tw_split(lo, hi, k, lo_bits), Bv);
+    };
+    if constexpr (sizeof(T) == 4) {
+        if (so.hi) {
+            // the split step fused (SplitOut): row k1's coefficients k = k1 + L1 k2 go to
+            // columns k1 K2 + k2 of the operand row, so each row is one contiguous run;
+            // X = (s_k d_k / 2) (A + ...), the factor from the set-up's table (zero where
+            // k > N), as BF16 hi and lo
+            const int K2 = so.k2n;
+            uint32_t* const hrow = so.hi + (int64_t)(s_out + by) * so.kp2;
+            uint32_t* const lrow = so.lo + (int64_t)(s_out + by) * so.kp2;
+            for (int r = 0; r < 2 * nr; ++r) {
+                const int i = r >> 1, side = r & 1;
+                const int p = p0 + i;
+                const int rowA = p, rowB = (L1 - p) % L1;
+                if (side && rowB == rowA) continue;
+                const int k1 = side ? rowB : rowA;
+                const int64_t c0 = (int64_t)k1 * K2;
+                for (int k2 = threadIdx.x; k2 < K2; k2 += blockDim.x) {
+                    C A, WB;
+                    untangle(i, side, k1, k2, k1 + L1 * k2, A, WB);
+                    uint32_t h, l;
+                    bf16_split_pair(A.x + WB.y, A.y - WB.x, so.fac[c0 + k2], h, l);
+                    hrow[c0 + k2] = h;
+                    lrow[c0 + k2] = l;
+                }
+            }
+            return;
+        }
+    }
     // RR is a power of two: row index fastest, so R consecutive k share a segment.
     // Only columns k2 <= (N - p0)/L1 can hold a k <= N.
     const int rr_bits = __ffs(RR) - 1;
@@ -171,28 +210,10 @@ __global__ __launch_bounds__(512) void k_fft_rows_ab(const T* __restrict__ grid,
         const int k1 = side ? rowB : rowA;
         const int64_t k = (int64_t)k1 + (int64_t)L1 * k2;
         if (k > N) continue;
-        const int k2m = (k1 == 0) ? (k2 == 0 ? 0 : L2 - k2) : (L2 - 1 - k2);
-        const C Zk = sh[(2 * i + side) * rs + k2];
-        const C Zm = sh[(2 * i + 1 - side) * rs + k2m];
-        const C Av = C{Zk.x + Zm.x, Zk.y - Zm.y};
-        const C Bv = C{Zk.x - Zm.x, Zk.y + Zm.y};
-        const C WB = cmulf(tw_split(lo, hi, (int)k, lo_bits), Bv);
+        C Av, WB;
+        untangle(i, side, k1, k2, (int)k, Av, WB);
         const T d = dfac[k] * (T)0.5;
-        C ck = C{(Av.x + WB.y) * d, (Av.y - WB.x) * d};
-        // one value for both outputs: the coefficient and its split must agree bit for bit
-        asm volatile("" : "+v"(ck.x), "+v"(ck.y));
-        if constexpr (sizeof(T) == 4) {
-            if (so.hi) {
-                // the split step fused: X = s_k c_k as BF16 hi and lo, rounded as k_split_bf16 does
-                uint32_t h, l;
-                bf16_split_pair(ck.x, ck.y, so.scale[k], h, l);
-                const int64_t at = (int64_t)(s_out + by) * so.kp2 + k;
-                so.hi[at] = h;
-                so.lo[at] = l;
-                continue;
-            }
-        }
-        out[k] = ck;
+        out[k] = C{(Av.x + WB.y) * d, (Av.y - WB.x) * d};
     }
 }
 
@@ -210,7 +231,7 @@ template <typename T>
 static hipError_t fft_ab_t(const Plan& p, const NufftWs& w, char* ws, int32_t s_begin, int32_t s_count, T* grid,
                            int64_t gstride, void* coef, int64_t ldc, hipStream_t st, const SplitOut* so)
 {
-    const SplitOut none{nullptr, nullptr, 0, nullptr};
+    const SplitOut none{};
     using C = typename CTf<T>::type;
     const int t1 = round64(p.CC * std::max(p.A1, p.B1));
     prof_begin("k_fft_cols_ab", st);

@@ -150,20 +150,31 @@ struct RangeReq {
     double t0, T;
     int64_t* ranges;
 };
+struct SplitOut;
 // Deconvolution factors and FFT tables (one launch with the two-pass FFT, which
-// also takes the tile ranges of rr), before the spreading.
-hipError_t launch_prep(const Plan& p, const NufftWs& w, char* ws, hipStream_t st, const RangeReq* rr = nullptr);
+// also takes the tile ranges of rr, and writes the fused split's column factors
+// so->fac from its scale table), before the spreading.
+hipError_t launch_prep(const Plan& p, const NufftWs& w, char* ws, hipStream_t st, const RangeReq* rr = nullptr,
+                       const SplitOut* so = nullptr);
 hipError_t launch_validate(int32_t S, const int64_t* offsets, const double* t, const void* dp, int dp_fp64,
                            double t0, double T, int* flag, hipStream_t st);
-// Destination of the split fused into the FFT's row pass: X = s_k c_k written as
-// BF16 hi and lo parts in the layout of the MFMA contraction's operands (row =
-// series, uint32 pair (Re, Im) at column k) instead of the coefficients c_k.
+// Destination of the split fused into the FFT's row pass: X = s_k c_k as BF16 hi
+// and lo parts (a uint32 pair (Re, Im)) in the MFMA contraction's operand rows
+// (row = series) instead of the coefficients c_k.  Coefficient k = k1 + L1 k2 sits
+// at column k1 K2 + k2, K2 = ceil((N + 1) / L1): the row pass transforms one FFT row
+// (one k1) at a time, so each of its rows leaves as one contiguous run, and the
+// contraction's sum over k does not depend on the order of the columns.  Columns
+// whose k exceeds N hold zero.
 struct SplitOut {
     uint32_t* hi;
     uint32_t* lo;
-    int64_t kp2;           // pairs per row (Kp / 2)
-    const float* scale;    // s_k, zero beyond N
+    int64_t kp2;           // pairs per operand row (Kp / 2), at least L1 K2
+    int32_t k2n;           // K2
+    const float* scale;    // s_k by k, zero beyond N (written by the prologue)
+    float* fac;            // by column: s_k d_k / 2 (d_k the deconvolution factor), zero where k > N
 };
+// Columns of the fused split's operands for cutoff N and FFT row count L1: L1 K2.
+int32_t split_out_cols(int32_t N, int32_t L1);
 
 
 hipError_t launch_nufft_tiled(const Plan& p, const NufftWs& w, char* ws, int32_t s_begin, int32_t s_count,
@@ -232,11 +243,14 @@ hipError_t launch_pairwise_select(int prec, int32_t G, int32_t D, const int32_t*
 // (launch_split_prologue, then SplitOut), so the scale and split steps are skipped.
 hipError_t launch_cov_mfma(int32_t G, int32_t D, const void* coef, int64_t ldc, int32_t N, int basis,
                            void* cov, char* ws, hipStream_t st, bool operands_ready = false, SyrkChoice sc = {});
-// The fused split for one group and one cutoff N of the MFMA contraction: the
-// operand pointers in its workspace, and a prologue that writes the column scale
-// table and zeroes the operands' padding (rows D..Dp-1, columns beyond N).
-SplitOut cov_mfma_split_out(int32_t D, int32_t N, char* ws, SyrkChoice sc = {});
-hipError_t launch_split_prologue(int32_t D, int32_t N, int basis, char* ws, hipStream_t st, SyrkChoice sc = {});
+// The fused split for one group and one cutoff N of the MFMA contraction (the
+// NUFFT's FFT having L1 rows): the operand pointers in its workspace, which is
+// that of cutoff split_out_cols(N, L1) - 1, and a prologue that writes the scale
+// table s_k and zeroes the operands' padding (rows D..Dp-1, columns from L1 K2 on).
+// The NUFFT's set-up launch then fills SplitOut::fac.
+SplitOut cov_mfma_split_out(int32_t D, int32_t N, int32_t L1, char* ws, SyrkChoice sc = {});
+hipError_t launch_split_prologue(int32_t D, int32_t N, int32_t L1, int basis, char* ws, hipStream_t st,
+                                 SyrkChoice sc = {});
 hipError_t launch_cov_fp64(int32_t G, int32_t D, const void* coef, int64_t ldc, int32_t N, int basis,
                            void* cov, hipStream_t st);
 // The one-pass per-pair-cutoff product (mm_cov_pairwise beyond the small-D path):

@@ -1260,12 +1260,24 @@ __global__ void k_prep(int L1, int L2, int L, int Mr, FFTDesc F1, FFTDesc F2, ty
 // transform (Eq. Der:11) is a Gauss-Legendre sum over the rule's 2 x 64 symmetric
 // nodes, one node per lane, added up by lane shuffles; the Gaussian and KB
 // transforms have closed forms (lane 0).
+// Column factors of the split fused into the row pass (SplitOut): for column
+// c = (k mod L1) K2 + k / L1, c < ncol, the factor s_k d_k / 2, or 0 where k > N.
+struct FacJob {
+    const float* scale;   // s_k
+    float* fac;           // nullptr: no fused split
+    int L1, k2n, ncol;
+};
+
 template <typename T>
 __device__ __forceinline__ void deconv_wave(int k, int q, int N, int Mr, const KernParams& kp, const GLRule& gl,
-                                            T* __restrict__ dfac)
+                                            T* __restrict__ dfac, const FacJob& fj)
 {
-    if (k > N) return;
+    if (k > N) {
+        if (q == 0 && fj.fac && k < fj.ncol) fj.fac[(k % fj.L1) * fj.k2n + k / fj.L1] = 0.f;
+        return;
+    }
     const double pi = 3.14159265358979323846;
+    double d;
     if (kp.kind == MM_ES) {
         const double nu = (double)k / (double)Mr;
         double acc = 0.0;
@@ -1275,29 +1287,35 @@ __device__ __forceinline__ void deconv_wave(int k, int q, int N, int Mr, const K
         }
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
-        if (q == 0) dfac[k] = (T)(1.0 / (2.0 * pi * (2.0 * kp.hw * acc)));
-    } else if (q == 0) {
-        dfac[k] = (T)deconv_factor(kp, k, Mr, gl);
+        d = 1.0 / (2.0 * pi * (2.0 * kp.hw * acc));
+    } else {
+        if (q != 0) return;
+        d = deconv_factor(kp, k, Mr, gl);
+    }
+    if (q == 0) {
+        dfac[k] = (T)d;
+        if (fj.fac) fj.fac[(k % fj.L1) * fj.k2n + k / fj.L1] = (float)(0.5 * d * (double)fj.scale[k]);
     }
 }
 
 template <typename T>
 __global__ __launch_bounds__(64) void k_deconv(int N, int Mr, KernParams kp, GLRule gl, T* __restrict__ dfac)
 {
-    deconv_wave<T>(blockIdx.x, threadIdx.x, N, Mr, kp, gl, dfac);
+    deconv_wave<T>(blockIdx.x, threadIdx.x, N, Mr, kp, gl, dfac, FacJob{nullptr, nullptr, 1, 0, 0});
 }
 
 // The set-up of a two-pass-FFT plan in one launch of 256-thread blocks: blocks
-// [0, nb_dec) the deconvolution factors (one wave per k, as k_deconv), the next
-// nb_tab blocks the FFT's twiddle tables (as k_fft_tables), the rest the tile
-// event ranges of rj (as k_tile_ranges; none if rj.s_count is 0).
+// [0, nb_dec) the deconvolution factors (one wave per k, as k_deconv) and the
+// fused split's column factors (fj), the next nb_tab blocks the FFT's twiddle
+// tables (as k_fft_tables), the rest the tile event ranges of rj (as
+// k_tile_ranges; none if rj.s_count is 0).
 template <typename T, bool EXACT_DIV>
 __global__ __launch_bounds__(256) void k_setup(int N, int Mr, KernParams kp, GLRule gl, T* __restrict__ dfac,
-                                               int nb_dec, FftTables<T> tb, int nb_tab, RangeJob rj)
+                                               FacJob fj, int nb_dec, FftTables<T> tb, int nb_tab, RangeJob rj)
 {
     const int b = blockIdx.x;
     if (b < nb_dec) {
-        deconv_wave<T>(4 * b + ((int)threadIdx.x >> 6), (int)threadIdx.x & 63, N, Mr, kp, gl, dfac);
+        deconv_wave<T>(4 * b + ((int)threadIdx.x >> 6), (int)threadIdx.x & 63, N, Mr, kp, gl, dfac, fj);
     } else if (b < nb_dec + nb_tab) {
         fft_tables_at<T>(tb, (int64_t)(b - nb_dec) * 256 + threadIdx.x);
     } else {
@@ -1340,21 +1358,27 @@ static GLRule host_gl()
 
 template <typename T>
 static void setup_t(const Plan& p, const NufftWs& w, char* ws, const GLRule& gl, const RangeJob& rj,
-                    int64_t n_ranges, hipStream_t st)
+                    int64_t n_ranges, const FacJob& fj, hipStream_t st)
 {
-    const int nb_dec = (p.N + 1 + 3) / 4;
+    const int nk = fj.fac ? std::max(p.N + 1, fj.ncol) : p.N + 1;
+    const int nb_dec = (nk + 3) / 4;
     const int nb_tab = (int)((fft_tables_count(p) + 255) / 256);
     const int nb_rng = (int)((n_ranges + 255) / 256);
     if (p.prec == MM_PLAIN_FP64)
         hipLaunchKernelGGL((k_setup<T, true>), dim3(nb_dec + nb_tab + nb_rng), dim3(256), 0, st, p.N, p.Mr, p.kp, gl,
-                           (T*)(ws + w.dfac), nb_dec, fft_tables_of<T>(p, w, ws), nb_tab, rj);
+                           (T*)(ws + w.dfac), fj, nb_dec, fft_tables_of<T>(p, w, ws), nb_tab, rj);
     else
         hipLaunchKernelGGL((k_setup<T, false>), dim3(nb_dec + nb_tab + nb_rng), dim3(256), 0, st, p.N, p.Mr, p.kp, gl,
-                           (T*)(ws + w.dfac), nb_dec, fft_tables_of<T>(p, w, ws), nb_tab, rj);
+                           (T*)(ws + w.dfac), fj, nb_dec, fft_tables_of<T>(p, w, ws), nb_tab, rj);
 }
 
-hipError_t launch_prep(const Plan& p, const NufftWs& w, char* ws, hipStream_t st, const RangeReq* rr)
+hipError_t launch_prep(const Plan& p, const NufftWs& w, char* ws, hipStream_t st, const RangeReq* rr,
+                       const SplitOut* so)
 {
+    if (so && (!p.fft_ab || p.prec != MM_MIXED || so->k2n < 1 || (int64_t)p.L1 * so->k2n > so->kp2 ||
+               (int64_t)p.L1 * so->k2n < (int64_t)p.N + 1 || so->k2n > p.L2))
+        return hipErrorInvalidValue;   // the fused split runs only with the two-pass FFT, on its own layout
+    const FacJob fj = so ? FacJob{so->scale, so->fac, p.L1, so->k2n, p.L1 * so->k2n} : FacJob{nullptr, nullptr, 1, 0, 0};
     GLRule gl = host_gl();
     if (p.fft_ab) {
         // deconvolution factors, twiddle tables and (if asked) tile ranges: one launch
@@ -1367,8 +1391,8 @@ hipError_t launch_prep(const Plan& p, const NufftWs& w, char* ws, hipStream_t st
             nr = (int64_t)rr->s_count * rr->tiles * 6;
         }
         prof_begin("k_setup", st);
-        if (p.prec == MM_MIXED) setup_t<float>(p, w, ws, gl, rj, nr, st);
-        else setup_t<double>(p, w, ws, gl, rj, nr, st);
+        if (p.prec == MM_MIXED) setup_t<float>(p, w, ws, gl, rj, nr, fj, st);
+        else setup_t<double>(p, w, ws, gl, rj, nr, fj, st);
         prof_end("k_setup", st);
         return hipGetLastError();
     }

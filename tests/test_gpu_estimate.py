@@ -139,19 +139,25 @@ def test_graph_with_coefficient_output_and_new_cutoffs(mm):
 @pytest.mark.parametrize("basis", ["dirichlet", "fejer"])
 @pytest.mark.parametrize("D,N,tune", [(300, 3000, None), (1100, 3000, None), (769, 3000, None), (300, 100, None),
                                       (1100, 3000, {"sigma": 1.55, "tile": 2048})])
-def test_fused_split_equals_two_calls(mm, basis, D, N, tune):
+def test_fused_split_agrees_with_two_calls(mm, basis, D, N, tune):
     """With no coefficient output, one group and one cutoff on the MFMA path, the
-    FFT's row pass writes the contraction's BF16 operands itself; the operands,
-    hence Sigma and R, must equal the two-call form's bit for bit (128- and
-    256-wide SYRK tiles, the smallest D of the 256-wide kernel, a short k range,
-    ragged last tile rows, empty series, the tuned plan), eagerly and as graph
-    replays, and the oracle on a few series."""
+    FFT's row pass writes the contraction's BF16 operands itself, row k1 of the FFT
+    matrix as one run of columns (coefficient k1 + L1 k2 at column k1 K2 + k2).
+    The contraction then sums the same products in another column order, so Sigma
+    and R must agree with the two-call form's to FP32 summation rounding (4e-6,
+    four times the mixed contraction's error against FP64 at D = 2000) rather than
+    bit for bit (128- and 256-wide SYRK tiles, the smallest D of the 256-wide
+    kernel, a short k range, ragged last tile rows, empty series, the tuned plan);
+    graph replays must equal the eager call bit for bit; and the oracle on a few
+    series."""
     w = synth.random_events(D, 0, 1500, seed=4040 + D + N, dp_dtype=torch.float32, device="cuda")
     c = mm.nufft1(w.offsets, w.t, w.dp, w.t0, w.T, N, "es", 1e-6, "mixed", tune)
     S1, R1 = mm.cov(c, 1, D, [N], basis)
     S2, R2, ws = mm.estimate(w.offsets, w.t, w.dp, w.t0, w.T, 1, D, [N], basis, "es", 1e-6, "mixed", tune)
     torch.cuda.synchronize()
-    assert same(S1, S2) and same(R1, R2)
+    assert relfro(S2.cpu().numpy(), S1.cpu().numpy()) <= 4e-6
+    assert relfro(R2.cpu().numpy(), R1.cpu().numpy()) <= 4e-6
+    assert torch.equal(S2, S2.transpose(-1, -2))
     out = (torch.empty_like(S2), torch.empty_like(R2))
     st = torch.cuda.Stream()
     for rep in range(3):
@@ -161,7 +167,7 @@ def test_fused_split_equals_two_calls(mm, basis, D, N, tune):
             mm.estimate(w.offsets, w.t, w.dp, w.t0, w.T, 1, D, [N], basis, "es", 1e-6, "mixed", tune, use_graph=True,
                         ws=ws, out=out)
         st.synchronize()
-        assert same(S1, out[0]) and same(R1, out[1]), rep
+        assert same(S2, out[0]) and same(R2, out[1]), rep
         torch.cuda.synchronize()
     mm.graph_cache_clear()
     # and against the oracle on four non-empty series (their block of Sigma and R)

@@ -31,8 +31,9 @@ def universe(mm):
     """The benchmark workload: 2000 assets, ~4.5e8 events, N = 50,000, mixed ES
     tol 1e-6, Fejer basis, the autotuned plan.  Sigma and R come from the call
     bench.py times (mm_estimate with the split fused into the FFT's row pass) and
-    must equal the two-call form's bit for bit; the coefficients for sampling
-    come from mm_nufft1."""
+    must agree with the two-call form's to FP32 summation rounding (the same
+    products summed in another column order); the coefficients for sampling come
+    from mm_nufft1."""
     from paper_2003_02842_amd.tune import LARGE_UNIVERSE, load_tuned
     w = synth.large_universe(device="cuda")
     N = w.Ns[0]
@@ -41,7 +42,8 @@ def universe(mm):
     cov2, corr2 = mm.cov(coef, 1, w.S, [N], "fejer", tune=tune)
     cov, corr, ws = mm.estimate(w.offsets, w.t, w.dp, w.t0, w.T, 1, w.S, [N], "fejer", "es", 1e-6, "mixed", tune)
     torch.cuda.synchronize()
-    assert torch.equal(cov, cov2) and torch.equal(torch.nan_to_num(corr), torch.nan_to_num(corr2))
+    assert relfro(cov.cpu().numpy(), cov2.cpu().numpy()) <= 4e-6
+    assert relfro(corr.cpu().numpy(), corr2.cpu().numpy()) <= 4e-6
     del cov2, corr2, ws
     return w, N, coef, cov[0, 0].cpu().numpy().astype(np.float64), corr[0, 0].cpu().numpy().astype(np.float64)
 
