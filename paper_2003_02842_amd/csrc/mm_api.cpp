@@ -355,8 +355,8 @@ mm_status mm_estimate(int32_t G, int32_t D, const int64_t* offsets, const double
     const NufftWs w = nufft_workspace(p, S);
     hipStream_t st = (hipStream_t)stream;
     // With no coefficient output, one group and one cutoff on the MFMA path, the
-    // FFT's row pass writes the contraction's BF16 operands directly (the same
-    // values, rounded the same way, as the split step would).
+    // FFT's row pass writes the contraction's BF16 operands directly, one FFT row
+    // per run of columns (SplitOut).
     const bool fuse = !coef_out && G == 1 && nN == 1 && prec == MM_MIXED && !use_fused(p, S) && p.fft_ab &&
                       !small_d_limit(D);
     const SplitOut so = fuse ? cov_mfma_split_out(D, Ns[0], p.L1, wsb + L.cov, sc) : SplitOut{};
