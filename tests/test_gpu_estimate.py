@@ -138,7 +138,7 @@ def test_graph_with_coefficient_output_and_new_cutoffs(mm):
 
 @pytest.mark.parametrize("basis", ["dirichlet", "fejer"])
 @pytest.mark.parametrize("D,N,tune", [(300, 3000, None), (1100, 3000, None), (769, 3000, None), (300, 100, None),
-                                      (1100, 3000, {"sigma": 1.55, "tile": 2048})])
+                                      (45, 700, None), (1100, 3000, {"sigma": 1.55, "tile": 2048})])
 def test_fused_split_agrees_with_two_calls(mm, basis, D, N, tune):
     """With no coefficient output, one group and one cutoff on the MFMA path, the
     FFT's row pass writes the contraction's BF16 operands itself, row k1 of the FFT
@@ -146,8 +146,9 @@ def test_fused_split_agrees_with_two_calls(mm, basis, D, N, tune):
     The contraction then sums the same products in another column order, so Sigma
     and R must agree with the two-call form's to FP32 summation rounding (4e-6,
     four times the mixed contraction's error against FP64 at D = 2000) rather than
-    bit for bit (128- and 256-wide SYRK tiles, the smallest D of the 256-wide
-    kernel, a short k range, ragged last tile rows, empty series, the tuned plan);
+    bit for bit (128- and 256-wide SYRK tiles, the smallest D of the MFMA path and
+    of the 256-wide kernel, a short k range, ragged last tile rows, empty series,
+    the tuned plan);
     graph replays must equal the eager call bit for bit; and the oracle on a few
     series."""
     w = synth.random_events(D, 0, 1500, seed=4040 + D + N, dp_dtype=torch.float32, device="cuda")
