@@ -82,6 +82,11 @@ __host__ __device__ constexpr int poly_degree_for_width(int w)
 {
     return w <= 2 ? 4 : (w <= 3 ? 5 : (w <= 5 ? 6 : (w <= 6 ? 7 : 8)));
 }
+// Widths of degree 8 also run at degree 7 where that fit leaves the error
+// estimate within tol (the planner's choice; the large-grid spreading kernels
+// have instances of both, the others evaluate degree 8 with a zero top term).
+constexpr int kPolyDegTop = 8;
+constexpr int kPolyDegLow = 7;
 
 struct Plan {
     int prec;            // mm_prec

@@ -544,7 +544,7 @@ __global__ __launch_bounds__(256) void k_spread(const double* __restrict__ t, co
 // (spread_tile_poly in mm_spread.h is the same algorithm for the fused kernel; this
 // kernel keeps its own copy, with its LDS arrays declared here, because as an inlined
 // call the compiler allocates it 117 VGPRs instead of 78, which costs occupancy.)
-template <typename DPT, int W, int PPT>
+template <typename DPT, int W, int PPT, int DEG>
 __global__ __launch_bounds__(256) void k_spread_poly(const double* __restrict__ t, const DPT* __restrict__ dp,
                                                      double t0, double scale, int Mr, double hw, PolyParams pp,
                                                      const int64_t* __restrict__ ranges, int nsub, int rsub,
@@ -555,7 +555,7 @@ __global__ __launch_bounds__(256) void k_spread_poly(const double* __restrict__ 
     constexpr int M = (W + 2) & ~1;                      // even ring, >= W + 1
     constexpr int EC = SpreadLds<W, PPT>::EC;                  // ~25 KB of LDS
     constexpr int SB = EC / 256;
-    constexpr int DEG = poly_degree_for_width(W);
+    static_assert(DEG >= 4 && DEG <= kMaxPolyDeg, "polynomial degree");
     __shared__ __align__(8) float ring[EC * M];
     __shared__ unsigned short keys[EC];
     __shared__ unsigned short first[TC + W + 2];
@@ -746,25 +746,24 @@ __global__ __launch_bounds__(256) void k_spread_poly(const double* __restrict__ 
 constexpr int kMomCells = 1024;   // cells of a sub-tile: 4 per thread
 constexpr int kMomEV = 4;         // events per thread per staged chunk
 
-template <int W>
+template <int W, int DEG>
 struct MomLds {
-    static constexpr int DEG = poly_degree_for_width(W);
     static constexpr int ND = DEG + 1;                          // moments per key (<= 9)
     static constexpr int NKP = kMomCells + 16;                  // keys, padded (W <= 17)
     static constexpr int EC = kMomEV * 256;                     // events per chunk
     static constexpr int stage_bytes = 8 * EC + 2 * EC + 2 * (NKP + 2);
-    static constexpr int mom_bytes = 36 * NKP;                  // per key: d 0-3, d 4-7 (float4), d 8
+    static constexpr int mom_bytes = (ND > 8 ? 36 : 32) * NKP;  // per key: d 0-3, d 4-7 (float4), d 8
     static constexpr int bytes = stage_bytes > mom_bytes ? stage_bytes : mom_bytes;
 };
 
-template <typename DPT, int W>
+template <typename DPT, int W, int DEG>
 __global__ __launch_bounds__(256) void k_spread_mom(const double* __restrict__ t, const DPT* __restrict__ dp,
                                                     double t0, double scale, int Mr, double hw, PolyParams pp,
                                                     const int64_t* __restrict__ ranges, int nsub, int rsub, int tc,
                                                     float dmin, int L2, int L2p, FastDiv divL2,
                                                     float* __restrict__ grid, int64_t grid_stride)
 {
-    using Lay = MomLds<W>;
+    using Lay = MomLds<W, DEG>;
     constexpr int ND = Lay::ND, NKP = Lay::NKP, EC = Lay::EC;
     constexpr int H = (W + 1) / 2;                              // taps with stored coefficients
     static_assert(W >= 2 && W <= 17 && ND <= 9, "key padding, moment layout");
@@ -909,7 +908,7 @@ __global__ __launch_bounds__(256) void k_spread_mom(const double* __restrict__ t
             for (int d = 0; d < 9; ++d) v[d] = d < ND ? mv[d] : 0.f;
             momA[k] = make_float4(v[0], v[1], v[2], v[3]);
             momB[k] = make_float4(v[4], v[5], v[6], v[7]);
-            momC[k] = v[8];
+            if (ND > 8) momC[k] = v[8];
         };
 #pragma unroll
         for (int g = 0; g < 4; ++g) put(tid + 256 * g, acc[g]);
@@ -928,7 +927,7 @@ __global__ __launch_bounds__(256) void k_spread_mom(const double* __restrict__ t
             for (int kk = 0; kk < W + 3; ++kk) {
                 const int k = 4 * tid + kk;
                 const float4 A = momA[k], B = momB[k];
-                const float m8 = momC[k];
+                const float m8 = ND > 8 ? momC[k] : 0.f;
                 const float mv[9] = {A.x, A.y, A.z, A.w, B.x, B.y, B.z, B.w, m8};
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
@@ -957,9 +956,9 @@ __global__ __launch_bounds__(256) void k_spread_mom(const double* __restrict__ t
     }
 }
 
-template <typename DPT, int W>
-static void spread_poly_w(const Plan& p, dim3 g, const double* t, const DPT* dp, double t0, double scale,
-                          const int64_t* ranges, int nsub, float* grid, int64_t gs, hipStream_t st)
+template <typename DPT, int W, int DEG>
+static void spread_poly_wd(const Plan& p, dim3 g, const double* t, const DPT* dp, double t0, double scale,
+                           const int64_t* ranges, int nsub, float* grid, int64_t gs, hipStream_t st)
 {
     const int rsub = p.tile / kRangeCells;
     const FastDiv dv = make_fastdiv((uint32_t)p.L2);
@@ -968,21 +967,37 @@ static void spread_poly_w(const Plan& p, dim3 g, const double* t, const DPT* dp,
     const float dmin = mom ? (float)p.mom_density : __builtin_huge_valf();
     prof_begin("k_spread_poly", st);
     if (p.tile <= 1024)
-        hipLaunchKernelGGL((k_spread_poly<DPT, W, 2>), g, dim3(256), 0, st, t, dp, t0, scale, p.Mr, p.kp.hw, p.pp,
-                           ranges, nsub, rsub, dmin, p.L2, p.L2p, dv, grid, gs);
+        hipLaunchKernelGGL((k_spread_poly<DPT, W, 2, DEG>), g, dim3(256), 0, st, t, dp, t0, scale, p.Mr, p.kp.hw,
+                           p.pp, ranges, nsub, rsub, dmin, p.L2, p.L2p, dv, grid, gs);
     else if (p.tile <= 2048)
-        hipLaunchKernelGGL((k_spread_poly<DPT, W, 4>), g, dim3(256), 0, st, t, dp, t0, scale, p.Mr, p.kp.hw, p.pp,
-                           ranges, nsub, rsub, dmin, p.L2, p.L2p, dv, grid, gs);
+        hipLaunchKernelGGL((k_spread_poly<DPT, W, 4, DEG>), g, dim3(256), 0, st, t, dp, t0, scale, p.Mr, p.kp.hw,
+                           p.pp, ranges, nsub, rsub, dmin, p.L2, p.L2p, dv, grid, gs);
     else
-        hipLaunchKernelGGL((k_spread_poly<DPT, W, 8>), g, dim3(256), 0, st, t, dp, t0, scale, p.Mr, p.kp.hw, p.pp,
-                           ranges, nsub, rsub, dmin, p.L2, p.L2p, dv, grid, gs);
+        hipLaunchKernelGGL((k_spread_poly<DPT, W, 8, DEG>), g, dim3(256), 0, st, t, dp, t0, scale, p.Mr, p.kp.hw,
+                           p.pp, ranges, nsub, rsub, dmin, p.L2, p.L2p, dv, grid, gs);
     prof_end("k_spread_poly", st);
     if (mom) {
         prof_begin("k_spread_mom", st);
-        hipLaunchKernelGGL((k_spread_mom<DPT, W>), g, dim3(256), 0, st, t, dp, t0, scale, p.Mr, p.kp.hw, p.pp, ranges,
-                           nsub, rsub, p.tile, dmin, p.L2, p.L2p, dv, grid, gs);
+        hipLaunchKernelGGL((k_spread_mom<DPT, W, DEG>), g, dim3(256), 0, st, t, dp, t0, scale, p.Mr, p.kp.hw, p.pp,
+                           ranges, nsub, rsub, p.tile, dmin, p.L2, p.L2p, dv, grid, gs);
         prof_end("k_spread_mom", st);
     }
+}
+
+// The plan's polynomial degree: the width's own (poly_degree_for_width), or one
+// less where the planner found that enough (kPolyDegLow, widths of degree-8 plans).
+template <typename DPT, int W>
+static void spread_poly_w(const Plan& p, dim3 g, const double* t, const DPT* dp, double t0, double scale,
+                          const int64_t* ranges, int nsub, float* grid, int64_t gs, hipStream_t st)
+{
+    constexpr int D0 = poly_degree_for_width(W);
+    if constexpr (D0 == kPolyDegTop) {
+        if (p.pp.deg == kPolyDegLow) {
+            spread_poly_wd<DPT, W, kPolyDegLow>(p, g, t, dp, t0, scale, ranges, nsub, grid, gs, st);
+            return;
+        }
+    }
+    spread_poly_wd<DPT, W, D0>(p, g, t, dp, t0, scale, ranges, nsub, grid, gs, st);
 }
 
 template <typename DPT>

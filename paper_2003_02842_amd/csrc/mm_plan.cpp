@@ -562,8 +562,19 @@ mm_status make_plan(int32_t N, mm_kernel kernel, double tol, mm_prec prec, const
         }
     }
     // the polynomials' own deviation from the kernel (relative to its peak, 1) adds to the bound
-    p->est_err = estimate_error(p->kp, sg, p->Mr, N, (prec == MM_MIXED) ? rounding_gain(kernel, p->poly) : 0.0) +
-                 (p->poly ? p->poly_err : 0.0);
+    const double est_kernel =
+        estimate_error(p->kp, sg, p->Mr, N, (prec == MM_MIXED) ? rounding_gain(kernel, p->poly) : 0.0);
+    // one degree less (one FMA per tap pair and one moment per key fewer) where its
+    // fit still leaves the whole estimate within tol
+    if (p->poly && p->pp.deg == kPolyDegTop) {
+        PolyParams low;
+        const double err = fit_poly(p->kp, kPolyDegLow, &low);
+        if (est_kernel + err <= tol) {
+            p->pp = low;
+            p->poly_err = err;
+        }
+    }
+    p->est_err = est_kernel + (p->poly ? p->poly_err : 0.0);
     int tile = (prec == MM_MIXED) ? 2048 : 1024;
     if (tune && tune->tile > 0) tile = tune->tile <= 1024 ? 1024 : (tune->tile <= 2048 ? 2048 : 4096);
     p->tile = tile;

@@ -49,8 +49,15 @@ static void check_plan(const Plan& p, int N, int kernel, double tol, int prec, c
               kn, p.kp.w, sg, p.poly);
     if (p.poly) {
         CHECK(prec == MM_MIXED && p.kp.w <= kMaxPolyTaps, "poly at w %d", p.kp.w);
-        CHECK(p.poly_err <= 0.05 * tol, "poly_err %g > tol/20 (tol %g)", p.poly_err, tol);
-        CHECK(p.pp.deg == poly_degree_for_width(p.kp.w), "poly degree %d at w %d", p.pp.deg, p.kp.w);
+        const int d0 = poly_degree_for_width(p.kp.w);
+        CHECK(p.pp.deg == d0 || (d0 == kPolyDegTop && p.pp.deg == kPolyDegLow), "poly degree %d at w %d", p.pp.deg,
+              p.kp.w);
+        // the width's own degree fits within tol/20; the lower one only within the estimate's headroom
+        if (p.pp.deg == d0) CHECK(p.poly_err <= 0.05 * tol, "poly_err %g > tol/20 (tol %g)", p.poly_err, tol);
+        else CHECK(p.est_err <= tol * (1 + 1e-12), "degree %d: est_err %g > tol %g", p.pp.deg, p.est_err, tol);
+        for (int j = 0; j < kMaxPolyTaps; ++j)
+            for (int k = p.pp.deg + 1; k <= kMaxPolyDeg; ++k)
+                CHECK(p.pp.c[j][k] == 0.f, "coefficient %d of tap %d above degree %d", k, j, p.pp.deg);
     }
     if (p.fft_ab) {
         CHECK((long)p.A1 * p.B1 == p.L1 && (long)p.A2 * p.B2 == p.L2, "codelet split %dx%d %dx%d of %d %d", p.A1, p.B1,
