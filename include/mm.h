@@ -51,7 +51,7 @@ typedef enum {
                                 out of reach at the requested oversampling */
     MM_ERR_WORKSPACE = 4,    /* ws_bytes below the size the *_workspace_size call reports */
     MM_ERR_HIP = 5,          /* a HIP runtime call failed */
-    MM_ERR_UNSUPPORTED = 6   /* a valid request this build does not implement */
+    MM_ERR_UNSUPPORTED = 6   /* a valid request the library does not implement */
 } mm_status;
 
 typedef enum { MM_DIRICHLET = 0, MM_FEJER = 1 } mm_basis;            /* Eq. Der:2 / Eq. Der:3 */

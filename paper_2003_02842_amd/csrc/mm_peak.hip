@@ -1,7 +1,7 @@
 // Measurement probes, not part of the estimator: the BF16 MFMA issue rate of
 // gfx950 with no memory traffic (v_mfma_f32_32x32x16_bf16 back to back on
 // independent accumulators) and a streaming copy, the achievable ceilings
-// against which the contraction and the HBM-bound kernels are judged beside the
+// against which the contraction and the HBM-bound kernels are compared beside the
 // datasheet peaks.  Built into their own library (libmm_peak.so); bench.py
 // calls them.
 #include <hip/hip_runtime.h>
