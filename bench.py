@@ -472,7 +472,7 @@ def main():
     if a.copy_calibration:
         return copy_calibration()
     if a.gpus != 1:
-        print("bench.py measures one GPU (the path is single-GPU); --gpus %d is not supported" % a.gpus, file=sys.stderr)
+        print("bench.py runs on exactly one GPU (the path is single-GPU); --gpus %d is not supported" % a.gpus, file=sys.stderr)
         return 2
     if a.workload == "pairwise":
         print(json.dumps(pairwise_bench(a)), flush=True)
